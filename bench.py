@@ -1,0 +1,192 @@
+"""Throughput of the DVM-BGK octree step on one MI355X.
+
+One step = one pass of the whole hot path over the state: transport across
+leaf faces for every discrete velocity, the FP64 moment reduction, the
+corrected-Maxwellian BGK relaxation (one fused kernel), then the global FP64
+conservation sums.  Default workload: 64^3 root cubes with a seeded 40% refined
+once (996,150 leaf cells), 24^3 velocities on [-6, 6]^3, FP32 f with FP64
+moments, first-order upwind, periodic Sod-like jump, tau from Kn = 0.01.
+
+Prints ONE JSON line: CVU/s (cell-velocity updates per second), the roofline
+of the fused step kernel (HIP events on the launch stream), and the FP64 CPU
+oracle timed on a bounded sample of the same construction.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DVM cell-velocity updates/s + % HBM roofline, FP64/FP32/hybrid, same error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_case(name):
+    from paper_1503_00707_amd import dvm as D
+    from paper_1503_00707_amd import inputs as I
+    w = I.workload(name)
+    lev, ijk = D.balance(w.forest)
+    import dataclasses
+    forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
+    solid = None
+    if w.solid_ball is not None:
+        cx, cy, cz, r, lv = w.solid_ball
+        solid = I.solid_flags(forest, (cx, cy, cz), r, lv)
+    return w, forest, solid
+
+
+def gpu_bench(args):
+    import torch
+
+    from paper_1503_00707_amd import dvm as D
+    from paper_1503_00707_amd import inputs as I
+
+    t0 = time.time()
+    w, forest, solid = build_case(args.workload)
+    mesh = D.Mesh(forest, solid)
+    t = mesh.tables()
+    prim = I.fields(w.fields, I.leaf_centres(forest)[t["input"]], **w.field_args)
+    prec = D.PREC_FP64 if args.precision == "fp64" else D.PREC_FP32
+    p = D.make_params(w.nv[0], w.vhi[0], precision=prec, scheme=w.scheme, collision=w.collision,
+                      tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall)
+    s = D.Solver(mesh, p)
+    s.init_maxwellian(prim)
+    del prim
+    dt = s.dt(w.cfl)
+    torch.cuda.synchronize()
+    log(f"[bench] {args.workload}: {s.n} cells x {s.nv} velocities, {args.precision}, "
+        f"{2 * s.sizes.f_bytes / 1e9:.1f} GB of f, setup {time.time() - t0:.1f}s")
+    s.global_sums()
+    rc, g0, _, _ = s.check()
+
+    def one_step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        s.step(1, dt=dt)
+        if ev is not None:
+            ev[1].record()
+        s.global_sums()
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(evs[i])
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = evs[0][0].elapsed_time(end)
+    k_ms = [a.elapsed_time(b) for a, b in evs]
+    rc, g1, bad, nsteps = s.check()
+    log(f"[bench] timed {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), "
+        f"step kernel mean {np.mean(k_ms):.3f} ms, status {rc}")
+    cvu = s.n * s.nv * args.steps / (total_ms / 1e3)
+    fbytes = 8 if prec == D.PREC_FP64 else 4
+    # algorithmic bytes of one fused-step launch: read f once, write f once per CVU
+    alg_bytes = 2 * fbytes * s.n * s.nv
+    k_mean_s = float(np.mean(k_ms)) / 1e3
+    achieved = alg_bytes / k_mean_s / 1e9
+    drift = np.abs(g1 - g0) / np.maximum(np.abs(g0), 1e-300)
+    return dict(cvu=cvu, total_ms=total_ms, k_ms=k_ms, achieved=achieved, alg_bytes=alg_bytes, n=s.n, nv=s.nv,
+                rc=rc, drift=drift, g0=g0, w=w, fbytes=fbytes, dt=dt)
+
+
+def cpu_baseline(args):
+    """FP64 oracle on the host cores: the same construction on 16^3 roots."""
+    from oracle import oracle as O
+    from paper_1503_00707_amd import inputs as I
+    name = "octree16_v24_p40"
+    w = I.workload(name)
+    lev, ijk = O.balance(w.forest)
+    import dataclasses
+    forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
+    cores = len(os.sched_getaffinity(0))
+    cores = min(cores, 16)
+    O.set_threads(cores)
+    m = O.Mesh(forest)
+    t = m.tables()
+    p = O.make_params(w.nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
+                      tau_or_kn=w.tau_or_kn)
+    s = O.Solver(m, p)
+    s.init_maxwellian(I.fields(w.fields, I.leaf_centres(forest)[t["input"]], **w.field_args))
+    dt = s.dt_cfl(w.cfl)
+    n_steps, t_used = 0, 0.0
+    while t_used < args.cpu_seconds and n_steps < 50:
+        t0 = time.perf_counter()
+        s.step(dt, 1)
+        t_used += time.perf_counter() - t0
+        n_steps += 1
+        log(f"[bench] oracle step {n_steps}: {t_used:.1f}s")
+    cvu = m.n_cells * s.nv * n_steps / t_used
+    return dict(value=cvu, unit="CVU/s", cores=int(O.get_threads()), kind="oracle",
+                sample=f"{name}: {m.n_cells} cells x {s.nv} velocities, FP64, {n_steps} steps, {t_used:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="octree64_v24_p40")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    r = gpu_bench(args)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    w = r["w"]
+    ms = r["total_ms"] / args.steps
+    out = {
+        "metric": METRIC,
+        "value": r["cvu"],
+        "unit": "CVU/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": r["n"], "velocities": r["nv"],
+                   "velocity_grid": f"{w.nv[0]}^3 on [{w.vlo[0]}, {w.vhi[0]}]^3",
+                   "scheme": "upwind1" if w.scheme == 0 else "muscl-minmod",
+                   "precision": "f stored FP32, moments/Maxwellian/correction FP64" if args.precision == "fp32"
+                   else "FP64", "tau": f"hard sphere, Kn={w.tau_or_kn}", "dt": r["dt"],
+                   "pct_hbm_roofline_whole_step": 100.0 * (2 * r["fbytes"] * r["n"] * r["nv"]) / (ms / 1e3) / 8e12},
+        "roofline": {"bound": "hbm", "kernel": "k_step (fused transport+moments+Maxwellian+BGK)",
+                     "achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_ms_mean": float(np.mean(r["k_ms"])), "algorithmic_bytes_per_launch": r["alg_bytes"]},
+        "conservation_drift_rel": {"mass": float(r["drift"][0]), "energy": float(r["drift"][4])},
+        "status": int(r["rc"]),
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

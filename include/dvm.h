@@ -1,0 +1,236 @@
+/*
+ * dvm.h -- C interface of the MI355X DVM-BGK octree library.
+ *
+ * The library advances the discrete-velocity (DVM) form of the kinetic
+ * equation (eq. 1 of Zabelok, Arslanbekov & Kolobov, arXiv:1503.00707) on a
+ * 2:1-balanced forest of octrees (section 2.1).  One step is
+ *   1. upwind finite-volume transport of f(x, xi) across leaf faces for every
+ *      discrete velocity (eq. 2, section 3.1), first order or minmod-MUSCL;
+ *   2. a per-cell FP64 reduction to the conserved moments (rho, rho u, E)
+ *      (the moment sums of the correction kernel, section 3.2);
+ *   3. BGK relaxation (the BGK form of section 4) toward a discrete
+ *      Maxwellian corrected by the polynomial P of eq. (6) so that mass,
+ *      momentum and energy are conserved to rounding (section 3.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status (DVM_OK or a negative DVM_ERR_*);
+ *     no C++ exception crosses the interface.  dvm_last_error() returns a
+ *     thread-local text for the last failure on the calling thread.
+ *   - Argument errors are detected synchronously, before anything is
+ *     enqueued.  Device-side conditions (a cell with rho <= 0, T <= 0 or NaN)
+ *     set a device flag that the synchronising dvm_check() reports as
+ *     DVM_ERR_NONPHYSICAL.
+ *   - Device work is enqueued on the caller's hipStream_t (passed as void*;
+ *     NULL is the default stream) and is asynchronous.
+ *   - Ownership: the caller owns every device buffer (allocated e.g. by
+ *     PyTorch) and keeps it alive while the solver uses it.  The library owns
+ *     only host objects, released by dvm_destroy_*.
+ *   - Geometry: leaf (level l, i, j, k) is the cube [i, i+1) x [j, j+1) x
+ *     [k, k+1) scaled by h0 * 2^-l; root cubes form an nx x ny x nz lattice.
+ *     Domain faces are ordered -x, +x, -y, +y, -z, +z.
+ *   - Velocity grid: cell centres xi_k = lo + (k + 1/2)(hi - lo)/N per axis
+ *     (section 3: f at cell centres of a uniform Cartesian velocity grid).
+ *     The device path requires the same even N on all axes and lo = -hi per
+ *     axis.  Internally f[cell][v] keeps the 8 velocity sign groups ("octants")
+ *     contiguous, (-,-,-) first and the z sign fastest (section 3.1, step 1);
+ *     inside an octant slot s = (ax*NH + ay)*NH + az, NH = N/2, addresses the
+ *     node with |xi_b| = (a_b + 1/2) d_b.  dvm_f_to_canonical() converts to
+ *     the canonical order i = (kx*N + ky)*N + kz.
+ */
+#ifndef DVM_H
+#define DVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define DVM_OK 0
+#define DVM_ERR_ARG (-1)            /* invalid argument */
+#define DVM_ERR_UNBALANCED (-2)     /* leaves violate the 2:1 rule */
+#define DVM_ERR_NOT_PARTITION (-3)  /* leaves overlap, leave a gap or leave the domain */
+#define DVM_ERR_WORKSPACE (-4)      /* a bound buffer is missing or too small */
+#define DVM_ERR_NONPHYSICAL (-5)    /* rho <= 0, T <= 0 or NaN met on the device */
+#define DVM_ERR_DEVICE (-6)         /* a HIP runtime call failed */
+#define DVM_ERR_UNSUPPORTED (-7)    /* valid but not provided by the device path */
+
+/* ---- domain boundary kinds (per domain face) ---- */
+#define DVM_BC_PERIODIC 0  /* both faces of an axis must be periodic */
+#define DVM_BC_INFLOW 1    /* ghost = corrected Maxwellian of the inflow state */
+#define DVM_BC_OUTFLOW 2   /* ghost = the cell's own f (zero gradient) */
+#define DVM_BC_WALL 3      /* diffuse wall at rest, temperature t_wall */
+
+/* ---- face kinds in the exported tables ---- */
+#define DVM_FACE_SAME 0     /* one neighbour of the same level */
+#define DVM_FACE_COARSER 1  /* one neighbour one level coarser */
+#define DVM_FACE_FINER 2    /* four neighbours one level finer, ascending Morton key */
+#define DVM_FACE_INFLOW 3
+#define DVM_FACE_OUTFLOW 4
+#define DVM_FACE_WALL 5     /* domain wall or a fluid-solid face */
+
+/* ---- solver options ---- */
+#define DVM_PREC_FP64 0         /* f stored and transported in FP64 */
+#define DVM_PREC_FP32 1         /* f in FP32; moments, Maxwellian, correction in FP64 */
+#define DVM_SCHEME_UPWIND1 0
+#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction */
+#define DVM_COLL_EXP 0          /* f' = Mt + (f* - Mt) exp(-dt/tau) */
+#define DVM_COLL_EULER 1        /* f' = f* + dt/tau (Mt - f*) */
+#define DVM_COLL_OFF 2          /* f' = f* */
+#define DVM_TAU_CONST 0         /* tau = tau_or_kn */
+#define DVM_TAU_HS 1            /* tau = Kn T^(-1/2) / rho (hard sphere) */
+
+typedef struct dvm_mesh dvm_mesh;
+typedef struct dvm_solver dvm_solver;
+
+typedef struct {
+    int32_t base[3];          /* root cubes per axis, each >= 1 */
+    double h0;                /* root cube edge, > 0 */
+    int32_t bc[6];            /* DVM_BC_* per domain face */
+    int64_t n_leaves;
+    const uint8_t *level;     /* [n_leaves], host */
+    const int32_t *ijk;       /* [n_leaves][3], host, coordinates at the leaf's level */
+    const uint8_t *solid;     /* [n_leaves] or NULL; nonzero = inside a body */
+} dvm_mesh_desc;
+
+typedef struct {
+    int64_t n_leaves;         /* all leaves */
+    int64_t n_cells;          /* fluid leaves (the cells that carry f) */
+    int32_t max_level;
+    double h_min;
+    int64_t n_faces[6];       /* count of faces of each DVM_FACE_* kind */
+} dvm_mesh_info_t;
+
+typedef struct {
+    int32_t nv;               /* velocity nodes per axis (even) */
+    double vmax[3];           /* grid on [-vmax, vmax] per axis */
+    int32_t precision;        /* DVM_PREC_* */
+    int32_t scheme;           /* DVM_SCHEME_* */
+    int32_t collision;        /* DVM_COLL_* */
+    int32_t tau_mode;         /* DVM_TAU_* */
+    double tau_or_kn;
+    double inflow[5];         /* rho, ux, uy, uz, T of the inflow state */
+    double t_wall;            /* diffuse-wall temperature */
+    int32_t check_every;      /* global sums every k steps (0: never) */
+} dvm_params;
+
+typedef struct {
+    size_t f_bytes;           /* one state buffer; two are bound (ping-pong) */
+    size_t moments_bytes;     /* FP64 [5][n_cells] */
+    size_t tables_bytes;      /* device mesh tables */
+    size_t ws_bytes;          /* ghost tables, flags, reduction partials */
+    int64_t n_cells;
+    int64_t nv_total;         /* N^3 */
+} dvm_sizes;
+
+typedef struct {
+    double sums[5];           /* sum_c V_c (rho, rho ux, rho uy, rho uz, E), FP64 */
+    int32_t nonphysical;      /* 1 if the device flag was raised */
+    int64_t steps;            /* steps taken since dvm_bind */
+} dvm_diag;
+
+/* Text of the last error on this thread ("" if none). */
+const char *dvm_last_error(void);
+
+/*
+ * dvm_balance -- refine a partition until the 2:1 rule holds between leaves
+ * that share a face, an edge or a corner (section 2.1: levels of direct and
+ * diagonal neighbours differ by at most one).  Periodic axes (bc) wrap.
+ * Writes at most `cap` leaves (level_out[cap], ijk_out[cap][3], host) in
+ * Morton order; *n_out is always set.  Returns DVM_ERR_WORKSPACE if cap is
+ * too small, DVM_ERR_NOT_PARTITION if the input is not a partition.
+ */
+int dvm_balance(const dvm_mesh_desc *d, int64_t cap, int64_t *n_out, uint8_t *level_out, int32_t *ijk_out);
+
+/*
+ * dvm_create_mesh -- validate a leaf list (exact partition, 2:1 balanced) and
+ * build the Morton ("N-order", section 2.1) cell order and the per-cell face
+ * tables used by the transport (the stencil of eq. 2, section 3.1 step 4).
+ * Host only; copies what it needs from *d.
+ */
+int dvm_create_mesh(const dvm_mesh_desc *d, dvm_mesh **out);
+int dvm_mesh_info(const dvm_mesh *m, dvm_mesh_info_t *out);
+
+/*
+ * dvm_mesh_export -- host copies of the tables, for tests.  Any pointer may be
+ * NULL.  Per fluid cell c (Morton rank): input[c] = index in the caller's
+ * leaf list, key[c] = Morton key on the finest lattice (x bit lowest),
+ * type[c][6] = DVM_FACE_*, nbr[c][6][4] = neighbour cells (-1 padding).
+ */
+int dvm_mesh_export(const dvm_mesh *m, int64_t *input, uint64_t *key, uint8_t *type, int32_t *nbr);
+void dvm_destroy_mesh(dvm_mesh *m);
+
+/*
+ * dvm_create_solver -- a solver for one mesh (which must outlive it).
+ * DVM_ERR_UNSUPPORTED for a velocity grid the device path does not provide.
+ */
+int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out);
+int dvm_buffer_sizes(const dvm_solver *s, dvm_sizes *out);
+
+/*
+ * dvm_bind -- device buffers owned by the caller: two state buffers of
+ * f_bytes (f_a holds the current state after binding), the FP64 moments
+ * [5][n_cells], the mesh tables and the workspace, sizes from
+ * dvm_buffer_sizes.  Pointers must be 256-byte aligned.
+ */
+int dvm_bind(dvm_solver *s, void *f_a, void *f_b, double *moments, void *tables, void *ws);
+
+/* dvm_upload -- copy the mesh tables and build the ghost tables (stream-ordered). */
+int dvm_upload(dvm_solver *s, void *stream);
+
+/*
+ * dvm_init_maxwellian -- f := corrected discrete Maxwellian (eq. 6) of the
+ * per-cell state prim[5][n_cells] = (rho, ux, uy, uz, T) (device, FP64), the
+ * collision's fixed point; moments := its conserved moments.
+ */
+int dvm_init_maxwellian(dvm_solver *s, const double *prim, void *stream);
+
+/*
+ * dvm_step -- n_steps full steps of size dt (dt <= 0: dt from the Courant
+ * number cfl, dt = cfl h_min / max_i(|xi_x| + |xi_y| + |xi_z|)), each
+ * transport (eq. 2) then BGK relaxation to the corrected Maxwellian.  After
+ * each step the moments buffer holds the FP64 moments of the post-transport
+ * state, which the collision conserves.
+ */
+int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream);
+
+/*
+ * dvm_global_sums -- enqueue the global FP64 conservation sums
+ * sum_c V_c (rho, rho u, E) of the moments buffer (a two-level reduction in a
+ * fixed order, so repeated runs agree bitwise; mass, momentum and energy are
+ * the quantities the correction of eq. 6 conserves).  Asynchronous; the
+ * result is read by dvm_check.
+ */
+int dvm_global_sums(dvm_solver *s, void *stream);
+
+/* dvm_dt -- the step dvm_step uses for a Courant number cfl. */
+int dvm_dt(const dvm_solver *s, double cfl, double *dt);
+
+/* dvm_current_f -- device pointer of the buffer holding the current state. */
+int dvm_current_f(const dvm_solver *s, void **f);
+
+/*
+ * dvm_moments -- FP64 conserved moments of the current state, out[5][n_cells]
+ * (device): rho, rho ux, rho uy, rho uz, E = w sum_i (1, xi_i, |xi_i|^2/2) f_i.
+ */
+int dvm_moments(dvm_solver *s, double *out, void *stream);
+
+/*
+ * dvm_check -- synchronises the stream, then reports the global FP64 sums
+ * sum_c V_c (rho, rho u, E) of the moments buffer and the nonphysical flag;
+ * returns DVM_ERR_NONPHYSICAL if the flag is set.
+ */
+int dvm_check(dvm_solver *s, void *stream, dvm_diag *out);
+
+/* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
+int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);
+int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_internal, void *stream);
+
+void dvm_destroy_solver(dvm_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVM_H */

@@ -1,0 +1,66 @@
+// kernels.h -- launch interface between the solver host code and the HIP
+// kernels (kernels.hip).  Plain structs passed by value as kernel arguments.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace dvm {
+
+struct VelGrid {
+    int nh;          // N/2 nodes per half axis
+    double dv[3];    // node spacing per axis
+    double w;        // dv[0]*dv[1]*dv[2]
+};
+
+struct StepArgs {
+    const void *f_in;
+    void *f_out;
+    double *mom;             // [5][n_cells]
+    const DevCell *cells;
+    const void *ghost_in;    // inflow Maxwellian, internal velocity order
+    const void *wall_m1;     // unit-density wall Maxwellian
+    const double *wall_den;  // [6] sum_{xi.n<0} |xi.n| M1 per face direction
+    int *flag;               // nonphysical flag
+    int64_t n_cells;
+    double dt;
+    double h0;
+    VelGrid g;
+    int collision;           // DVM_COLL_*
+    int tau_mode;            // DVM_TAU_*
+    double tau_or_kn;
+    int xcd_group;           // consecutive cells kept on one XCD (>= 1)
+};
+
+struct InitArgs {
+    const double *prim;      // [5][n] rho, ux, uy, uz, T; NULL: use prim0
+    double prim0[5];
+    void *f_out;             // [n][NV] internal order
+    double *mom;             // [5][n] or NULL
+    int *flag;
+    int64_t n;
+    VelGrid g;
+};
+
+// Kernel-configuration choice for one (precision, N) pair.
+struct StepConfig {
+    int threads;     // workgroup size
+    int xcd_group;
+};
+
+// All return hipError_t of the launch (hipErrorInvalidValue: no kernel for N).
+hipError_t launch_step(bool fp64, const StepArgs &a, const StepConfig &cfg, hipStream_t st);
+hipError_t launch_init(bool fp64, const InitArgs &a, hipStream_t st);
+hipError_t launch_moments(bool fp64, const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st);
+hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid &g, hipStream_t st);
+hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
+                              int n_part, double *out, hipStream_t st);
+hipError_t launch_to_canonical(bool fp64, bool to_canon, const void *src, void *dst, int64_t n, int nh,
+                               hipStream_t st);
+bool have_kernel(bool fp64, int nh, int threads);
+int default_threads(bool fp64, int nh);
+
+}  // namespace dvm

@@ -1,0 +1,314 @@
+// solver.cpp -- host side of the solver: argument checks, buffer layout,
+// kernel launches on the caller's stream.  Holds no device memory of its own:
+// every buffer is bound by the caller (dvm_bind).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace dvm;
+
+namespace {
+
+constexpr int kPartials = 1024;  // blocks of the first global-sum stage
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(DVM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct dvm_solver {
+    const dvm_mesh *m = nullptr;
+    dvm_params p{};
+    bool fp64 = false;
+    int nh = 0;
+    int64_t nv = 0;
+    int64_t n = 0;
+    VelGrid g{};
+    StepConfig cfg{};
+    size_t f_bytes = 0, mom_bytes = 0, tab_bytes = 0, ws_bytes = 0;
+    // workspace sections (byte offsets)
+    size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *mom = nullptr;
+    DevCell *tables = nullptr;
+    char *ws = nullptr;
+    bool uploaded = false;
+    int64_t steps = 0;
+    bool has_inflow = false, has_wall = false;
+
+    void *gin() const { return ws + off_gin; }
+    void *m1() const { return ws + off_m1; }
+    double *den() const { return reinterpret_cast<double *>(ws + off_den); }
+    int *flag() const { return reinterpret_cast<int *>(ws + off_flag); }
+    double *partials() const { return reinterpret_cast<double *>(ws + off_part); }
+    double *sums() const { return reinterpret_cast<double *>(ws + off_sums); }
+};
+
+static hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
+
+static double max_speed_sum(const dvm_solver *s) {
+    double r = 0.0;
+    for (int b = 0; b < 3; ++b) r += (s->nh - 0.5) * s->g.dv[b];
+    return r;
+}
+
+extern "C" {
+
+int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) {
+    clear_error();
+    if (!m || !p || !out) return fail(DVM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (p->nv < 2 || p->nv % 2) return fail(DVM_ERR_UNSUPPORTED, "nv = %d: the device path needs an even N", p->nv);
+    for (int b = 0; b < 3; ++b)
+        if (!(p->vmax[b] > 0)) return fail(DVM_ERR_ARG, "vmax[%d] must be > 0", b);
+    if (p->precision != DVM_PREC_FP64 && p->precision != DVM_PREC_FP32) return fail(DVM_ERR_ARG, "bad precision");
+    if (p->scheme != DVM_SCHEME_UPWIND1 && p->scheme != DVM_SCHEME_MUSCL) return fail(DVM_ERR_ARG, "bad scheme");
+    if (p->scheme == DVM_SCHEME_MUSCL) return fail(DVM_ERR_UNSUPPORTED, "MUSCL is not provided by the device path yet");
+    if (p->collision < DVM_COLL_EXP || p->collision > DVM_COLL_OFF) return fail(DVM_ERR_ARG, "bad collision mode");
+    if (p->tau_mode != DVM_TAU_CONST && p->tau_mode != DVM_TAU_HS) return fail(DVM_ERR_ARG, "bad tau mode");
+    if (p->collision != DVM_COLL_OFF && !(p->tau_or_kn > 0)) return fail(DVM_ERR_ARG, "tau_or_kn must be > 0");
+    const bool fp64 = p->precision == DVM_PREC_FP64;
+    const int nh = p->nv / 2;
+    const int thr = default_threads(fp64, nh);
+    if (!thr) return fail(DVM_ERR_UNSUPPORTED, "no device kernel for N = %d (have 4, 8, 12, 16, 24)", p->nv);
+    dvm_solver *s = new (std::nothrow) dvm_solver();
+    if (!s) return fail(DVM_ERR_ARG, "out of host memory");
+    s->m = m;
+    s->p = *p;
+    s->fp64 = fp64;
+    s->nh = nh;
+    s->nv = int64_t(p->nv) * p->nv * p->nv;
+    s->n = int64_t(m->cells.size());
+    s->g.nh = nh;
+    s->g.w = 1.0;
+    for (int b = 0; b < 3; ++b) {
+        s->g.dv[b] = 2.0 * p->vmax[b] / p->nv;
+        s->g.w *= s->g.dv[b];
+    }
+    s->cfg.threads = thr;
+    s->cfg.xcd_group = 1;
+    s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
+    s->has_wall = m->n_faces[DVM_FACE_WALL] > 0;
+    const size_t fs = fp64 ? 8 : 4;
+    s->f_bytes = align256(size_t(s->n) * size_t(s->nv) * fs);
+    s->mom_bytes = align256(size_t(5) * size_t(s->n) * 8);
+    s->tab_bytes = align256(size_t(s->n) * sizeof(DevCell));
+    size_t o = 0;
+    s->off_gin = o;  o += align256(size_t(s->nv) * fs);
+    s->off_m1 = o;   o += align256(size_t(s->nv) * fs);
+    s->off_den = o;  o += align256(6 * 8);
+    s->off_flag = o; o += 256;
+    s->off_part = o; o += align256(size_t(kPartials) * 5 * 8);
+    s->off_sums = o; o += 256;
+    s->ws_bytes = o;
+    *out = s;
+    return DVM_OK;
+}
+
+int dvm_buffer_sizes(const dvm_solver *s, dvm_sizes *out) {
+    clear_error();
+    if (!s || !out) return fail(DVM_ERR_ARG, "null argument");
+    out->f_bytes = s->f_bytes;
+    out->moments_bytes = s->mom_bytes;
+    out->tables_bytes = s->tab_bytes;
+    out->ws_bytes = s->ws_bytes;
+    out->n_cells = s->n;
+    out->nv_total = s->nv;
+    return DVM_OK;
+}
+
+int dvm_bind(dvm_solver *s, void *f_a, void *f_b, double *moments, void *tables, void *ws) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    void *ptrs[5] = {f_a, f_b, moments, tables, ws};
+    for (void *q : ptrs) {
+        if (!q) return fail(DVM_ERR_WORKSPACE, "a buffer is NULL");
+        if (reinterpret_cast<uintptr_t>(q) & 255) return fail(DVM_ERR_ARG, "buffers must be 256-byte aligned");
+    }
+    if (f_a == f_b) return fail(DVM_ERR_ARG, "the two state buffers must differ");
+    s->f[0] = f_a;
+    s->f[1] = f_b;
+    s->cur = 0;
+    s->mom = moments;
+    s->tables = static_cast<DevCell *>(tables);
+    s->ws = static_cast<char *>(ws);
+    s->uploaded = false;
+    s->steps = 0;
+    return DVM_OK;
+}
+
+int dvm_upload(dvm_solver *s, void *stream) {
+    clear_error();
+    if (!s || !s->ws) return fail(DVM_ERR_WORKSPACE, "solver not bound");
+    hipStream_t st = S(stream);
+    hipError_t e = hipMemcpyAsync(s->tables, s->m->table.data(), s->m->table.size() * sizeof(DevCell),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    e = hipMemsetAsync(s->ws, 0, s->ws_bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(ws)");
+    InitArgs a{};
+    a.prim = nullptr;
+    a.n = 1;
+    a.g = s->g;
+    a.flag = s->flag();
+    a.mom = nullptr;
+    if (s->has_inflow) {
+        for (int k = 0; k < 5; ++k) a.prim0[k] = s->p.inflow[k];
+        a.f_out = s->gin();
+        e = launch_init(s->fp64, a, st);
+        if (e != hipSuccess) return hip_fail(e, "inflow ghost");
+    }
+    if (s->has_wall) {
+        const double pw[5] = {1.0, 0.0, 0.0, 0.0, s->p.t_wall};
+        for (int k = 0; k < 5; ++k) a.prim0[k] = pw[k];
+        a.f_out = s->m1();
+        e = launch_init(s->fp64, a, st);
+        if (e != hipSuccess) return hip_fail(e, "wall Maxwellian");
+        e = launch_wall_den(s->fp64, s->m1(), s->den(), s->g, st);
+        if (e != hipSuccess) return hip_fail(e, "wall denominators");
+    }
+    // the host table must stay valid until the copy has been consumed
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    s->uploaded = true;
+    return DVM_OK;
+}
+
+int dvm_init_maxwellian(dvm_solver *s, const double *prim, void *stream) {
+    clear_error();
+    if (!s || !prim) return fail(DVM_ERR_ARG, "null argument");
+    if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
+    InitArgs a{};
+    a.prim = prim;
+    a.n = s->n;
+    a.g = s->g;
+    a.flag = s->flag();
+    a.mom = s->mom;
+    s->cur = 0;
+    a.f_out = s->f[0];
+    hipError_t e = launch_init(s->fp64, a, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "init");
+    s->steps = 0;
+    return DVM_OK;
+}
+
+int dvm_dt(const dvm_solver *s, double cfl, double *dt) {
+    clear_error();
+    if (!s || !dt) return fail(DVM_ERR_ARG, "null argument");
+    if (!(cfl > 0)) return fail(DVM_ERR_ARG, "cfl must be > 0");
+    *dt = cfl * s->m->h_min / max_speed_sum(s);
+    return DVM_OK;
+}
+
+int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
+    if (n_steps < 0) return fail(DVM_ERR_ARG, "n_steps < 0");
+    if (!(dt > 0)) {
+        int rc = dvm_dt(s, cfl, &dt);
+        if (rc) return rc;
+    }
+    StepArgs a{};
+    a.mom = s->mom;
+    a.cells = s->tables;
+    a.ghost_in = s->gin();
+    a.wall_m1 = s->m1();
+    a.wall_den = s->den();
+    a.flag = s->flag();
+    a.n_cells = s->n;
+    a.dt = dt;
+    a.h0 = s->m->h0;
+    a.g = s->g;
+    a.collision = s->p.collision;
+    a.tau_mode = s->p.tau_mode;
+    a.tau_or_kn = s->p.tau_or_kn;
+    a.xcd_group = s->cfg.xcd_group;
+    hipStream_t st = S(stream);
+    for (int it = 0; it < n_steps; ++it) {
+        a.f_in = s->f[s->cur];
+        a.f_out = s->f[s->cur ^ 1];
+        hipError_t e = launch_step(s->fp64, a, s->cfg, st);
+        if (e != hipSuccess) return hip_fail(e, "step");
+        s->cur ^= 1;
+        s->steps++;
+        if (s->p.check_every > 0 && s->steps % s->p.check_every == 0) {
+            e = launch_global_sums(s->mom, s->tables, s->n, s->m->h0, s->partials(), kPartials, s->sums(), st);
+            if (e != hipSuccess) return hip_fail(e, "global sums");
+        }
+    }
+    return DVM_OK;
+}
+
+int dvm_global_sums(dvm_solver *s, void *stream) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
+    hipError_t e = launch_global_sums(s->mom, s->tables, s->n, s->m->h0, s->partials(), kPartials, s->sums(), S(stream));
+    if (e != hipSuccess) return hip_fail(e, "global sums");
+    return DVM_OK;
+}
+
+int dvm_current_f(const dvm_solver *s, void **f) {
+    clear_error();
+    if (!s || !f) return fail(DVM_ERR_ARG, "null argument");
+    *f = s->f[s->cur];
+    return DVM_OK;
+}
+
+int dvm_moments(dvm_solver *s, double *out, void *stream) {
+    clear_error();
+    if (!s || !out) return fail(DVM_ERR_ARG, "null argument");
+    if (!s->f[0]) return fail(DVM_ERR_WORKSPACE, "solver not bound");
+    hipError_t e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "moments");
+    return DVM_OK;
+}
+
+int dvm_check(dvm_solver *s, void *stream, dvm_diag *out) {
+    clear_error();
+    if (!s || !out) return fail(DVM_ERR_ARG, "null argument");
+    if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
+    hipStream_t st = S(stream);
+    hipError_t e = launch_global_sums(s->mom, s->tables, s->n, s->m->h0, s->partials(), kPartials, s->sums(), st);
+    if (e != hipSuccess) return hip_fail(e, "global sums");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int flag = 0;
+    e = hipMemcpy(out->sums, s->sums(), 5 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&flag, s->flag(), sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(diag)");
+    out->nonphysical = flag != 0;
+    out->steps = s->steps;
+    if (flag) return fail(DVM_ERR_NONPHYSICAL, "a cell reached rho <= 0, T <= 0 or NaN");
+    return DVM_OK;
+}
+
+int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream) {
+    clear_error();
+    if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
+    hipError_t e = launch_to_canonical(s->fp64, true, f_internal, f_canon, s->n, s->nh, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "to_canonical");
+    return DVM_OK;
+}
+
+int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_internal, void *stream) {
+    clear_error();
+    if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
+    hipError_t e = launch_to_canonical(s->fp64, false, f_canon, f_internal, s->n, s->nh, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "from_canonical");
+    return DVM_OK;
+}
+
+void dvm_destroy_solver(dvm_solver *s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+"""ctypes binding of libdvm.so (include/dvm.h): argument marshalling only.
+
+Every step of the DVM path runs in the HIP library; PyTorch supplies device
+memory (torch.empty on the GPU) and the stream.  The binding raises if the
+built library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdvm.so")
+
+OK, ERR_ARG, ERR_UNBALANCED, ERR_NOT_PARTITION, ERR_WORKSPACE, ERR_NONPHYSICAL, ERR_DEVICE, ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+PREC_FP64, PREC_FP32 = 0, 1
+SCHEME_UPWIND1, SCHEME_MUSCL = 0, 1
+COLL_EXP, COLL_EULER, COLL_OFF = 0, 1, 2
+TAU_CONST, TAU_HS = 0, 1
+
+EXPORTED = [
+    "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
+    "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
+    "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
+    "dvm_destroy_solver",
+]
+
+
+class DvmError(RuntimeError):
+    def __init__(self, code: int, what: str, text: str):
+        super().__init__(f"{what} failed with {code}: {text}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("base", C.c_int32 * 3), ("h0", C.c_double), ("bc", C.c_int32 * 6), ("n_leaves", C.c_int64),
+                ("level", C.c_void_p), ("ijk", C.c_void_p), ("solid", C.c_void_p)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_leaves", C.c_int64), ("n_cells", C.c_int64), ("max_level", C.c_int32), ("h_min", C.c_double),
+                ("n_faces", C.c_int64 * 6)]
+
+
+class Params(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("vmax", C.c_double * 3), ("precision", C.c_int32), ("scheme", C.c_int32),
+                ("collision", C.c_int32), ("tau_mode", C.c_int32), ("tau_or_kn", C.c_double),
+                ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("f_bytes", C.c_size_t), ("moments_bytes", C.c_size_t), ("tables_bytes", C.c_size_t),
+                ("ws_bytes", C.c_size_t), ("n_cells", C.c_int64), ("nv_total", C.c_int64)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("sums", C.c_double * 5), ("nonphysical", C.c_int32), ("steps", C.c_int64)]
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1503_00707_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.dvm_last_error.restype = C.c_char_p
+        L.dvm_balance.argtypes = [C.POINTER(MeshDesc), C.c_int64, C.POINTER(C.c_int64), P, P]
+        L.dvm_create_mesh.argtypes = [C.POINTER(MeshDesc), C.POINTER(P)]
+        L.dvm_mesh_info.argtypes = [P, C.POINTER(MeshInfo)]
+        L.dvm_mesh_export.argtypes = [P, P, P, P, P]
+        L.dvm_destroy_mesh.argtypes = [P]
+        L.dvm_destroy_mesh.restype = None
+        L.dvm_create_solver.argtypes = [P, C.POINTER(Params), C.POINTER(P)]
+        L.dvm_buffer_sizes.argtypes = [P, C.POINTER(Sizes)]
+        L.dvm_bind.argtypes = [P, P, P, P, P, P]
+        L.dvm_upload.argtypes = [P, P]
+        L.dvm_init_maxwellian.argtypes = [P, P, P]
+        L.dvm_step.argtypes = [P, C.c_int32, C.c_double, C.c_double, P]
+        L.dvm_dt.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
+        L.dvm_global_sums.argtypes = [P, P]
+        L.dvm_current_f.argtypes = [P, C.POINTER(P)]
+        L.dvm_moments.argtypes = [P, P, P]
+        L.dvm_check.argtypes = [P, P, C.POINTER(Diag)]
+        L.dvm_f_to_canonical.argtypes = [P, P, P, P]
+        L.dvm_f_from_canonical.argtypes = [P, P, P, P]
+        L.dvm_destroy_solver.argtypes = [P]
+        L.dvm_destroy_solver.restype = None
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise DvmError(rc, what, lib().dvm_last_error().decode())
+
+
+def _desc(forest, solid=None):
+    lev = np.ascontiguousarray(forest.level, np.uint8)
+    ijk = np.ascontiguousarray(forest.ijk, np.int32).reshape(-1)
+    sol = None if solid is None else np.ascontiguousarray(solid, np.uint8)
+    d = MeshDesc()
+    for a in range(3):
+        d.base[a] = int(forest.base[a])
+    d.h0 = float(forest.h0)
+    for f in range(6):
+        d.bc[f] = int(forest.bc[f])
+    d.n_leaves = int(lev.shape[0])
+    d.level = lev.ctypes.data
+    d.ijk = ijk.ctypes.data
+    d.solid = None if sol is None else sol.ctypes.data
+    return d, (lev, ijk, sol)
+
+
+def balance(forest):
+    """2:1 balance (faces, edges, corners); returns (level, ijk) in Morton order."""
+    d, keep = _desc(forest)
+    n = C.c_int64(0)
+    rc = lib().dvm_balance(C.byref(d), 0, C.byref(n), None, None)
+    if rc not in (OK, ERR_WORKSPACE):
+        _check(rc, "dvm_balance")
+    lev = np.zeros(n.value, np.uint8)
+    ijk = np.zeros((n.value, 3), np.int32)
+    _check(lib().dvm_balance(C.byref(d), n.value, C.byref(n), lev.ctypes.data, ijk.ctypes.data), "dvm_balance")
+    return lev, ijk
+
+
+class Mesh:
+    def __init__(self, forest, solid: Optional[np.ndarray] = None):
+        d, keep = _desc(forest, solid)
+        h = C.c_void_p()
+        _check(lib().dvm_create_mesh(C.byref(d), C.byref(h)), "dvm_create_mesh")
+        self.h = h
+        self.forest = forest
+        info = MeshInfo()
+        _check(lib().dvm_mesh_info(h, C.byref(info)), "dvm_mesh_info")
+        self.n_leaves, self.n_cells = int(info.n_leaves), int(info.n_cells)
+        self.h_min, self.max_level = float(info.h_min), int(info.max_level)
+        self.n_faces = list(info.n_faces)
+
+    def tables(self):
+        n = self.n_cells
+        inp = np.zeros(n, np.int64)
+        key = np.zeros(n, np.uint64)
+        ty = np.zeros((n, 6), np.uint8)
+        nb = np.zeros((n, 6, 4), np.int32)
+        _check(lib().dvm_mesh_export(self.h, inp.ctypes.data, key.ctypes.data, ty.ctypes.data, nb.ctypes.data),
+               "dvm_mesh_export")
+        return dict(input=inp, key=key, type=ty, nbr=nb)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().dvm_destroy_mesh(self.h)
+            self.h = None
+
+
+def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=COLL_EXP, tau_mode=TAU_CONST,
+                tau_or_kn=0.1, inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, check_every=0) -> Params:
+    p = Params()
+    p.nv = int(nv)
+    vm = (vmax,) * 3 if np.isscalar(vmax) else tuple(vmax)
+    for a in range(3):
+        p.vmax[a] = float(vm[a])
+    p.precision, p.scheme, p.collision, p.tau_mode = int(precision), int(scheme), int(collision), int(tau_mode)
+    p.tau_or_kn = float(tau_or_kn)
+    for a in range(5):
+        p.inflow[a] = float(inflow[a])
+    p.t_wall = float(t_wall)
+    p.check_every = int(check_every)
+    return p
+
+
+class Solver:
+    """Owns the torch device buffers of one solver and drives the C interface."""
+
+    def __init__(self, mesh: Mesh, params: Params, device="cuda"):
+        import torch
+        self.torch = torch
+        self.mesh = mesh
+        self.params = params
+        h = C.c_void_p()
+        _check(lib().dvm_create_solver(mesh.h, C.byref(params), C.byref(h)), "dvm_create_solver")
+        self.h = h
+        sz = Sizes()
+        _check(lib().dvm_buffer_sizes(h, C.byref(sz)), "dvm_buffer_sizes")
+        self.sizes = sz
+        self.n, self.nv = int(sz.n_cells), int(sz.nv_total)
+        self.fdtype = torch.float64 if params.precision == PREC_FP64 else torch.float32
+        dev = torch.device(device)
+
+        def buf(nbytes):  # 256-byte aligned: the caching allocator aligns to 512
+            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+
+        self.f_a, self.f_b = buf(sz.f_bytes), buf(sz.f_bytes)
+        self.mom = torch.empty((5, self.n), dtype=torch.float64, device=dev)
+        self.tables_buf = buf(sz.tables_bytes)
+        self.ws = buf(sz.ws_bytes)
+        _check(lib().dvm_bind(h, self.f_a.data_ptr(), self.f_b.data_ptr(), self.mom.data_ptr(),
+                              self.tables_buf.data_ptr(), self.ws.data_ptr()), "dvm_bind")
+        _check(lib().dvm_upload(h, self.stream()), "dvm_upload")
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def init_maxwellian(self, prim):
+        t = self.torch.as_tensor(np.ascontiguousarray(prim, np.float64)).to("cuda")
+        self._prim = t
+        _check(lib().dvm_init_maxwellian(self.h, t.data_ptr(), self.stream()), "dvm_init_maxwellian")
+
+    def step(self, n=1, dt=0.0, cfl=0.5):
+        _check(lib().dvm_step(self.h, int(n), float(dt), float(cfl), self.stream()), "dvm_step")
+
+    def global_sums(self):
+        _check(lib().dvm_global_sums(self.h, self.stream()), "dvm_global_sums")
+
+    def dt(self, cfl):
+        out = C.c_double()
+        _check(lib().dvm_dt(self.h, float(cfl), C.byref(out)), "dvm_dt")
+        return out.value
+
+    def current(self):
+        p = C.c_void_p()
+        _check(lib().dvm_current_f(self.h, C.byref(p)), "dvm_current_f")
+        return self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+
+    def f_canonical(self):
+        """current state as a [n, N^3] torch tensor in canonical velocity order"""
+        out = self.torch.empty((self.n, self.nv), dtype=self.fdtype, device="cuda")
+        _check(lib().dvm_f_to_canonical(self.h, self.current().data_ptr(), out.data_ptr(), self.stream()),
+               "dvm_f_to_canonical")
+        return out
+
+    def set_f_canonical(self, f):
+        t = self.torch.as_tensor(np.ascontiguousarray(f)).to(device="cuda", dtype=self.fdtype)
+        _check(lib().dvm_f_from_canonical(self.h, t.data_ptr(), self.current().data_ptr(), self.stream()),
+               "dvm_f_from_canonical")
+        self.torch.cuda.synchronize()
+
+    def moments(self):
+        out = self.torch.empty((5, self.n), dtype=self.torch.float64, device="cuda")
+        _check(lib().dvm_moments(self.h, out.data_ptr(), self.stream()), "dvm_moments")
+        return out
+
+    def check(self):
+        d = Diag()
+        rc = lib().dvm_check(self.h, self.stream(), C.byref(d))
+        if rc not in (OK, ERR_NONPHYSICAL):
+            _check(rc, "dvm_check")
+        return rc, np.array(d.sums[:]), bool(d.nonphysical), int(d.steps)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().dvm_destroy_solver(self.h)
+            self.h = None

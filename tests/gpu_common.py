@@ -1,0 +1,82 @@
+"""Shared helpers of the GPU tests: run the HIP path (through the C interface)
+and the FP64 oracle on the same seeded inputs and compare."""
+import dataclasses
+import math
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+
+
+def balanced(forest):
+    lev, ijk = O.balance(forest)
+    return dataclasses.replace(forest, level=lev, ijk=ijk)
+
+
+@dataclasses.dataclass
+class Case:
+    forest: object
+    nv: int
+    vmax: float
+    scheme: int = I.SCHEME_UPWIND1
+    collision: int = I.COLL_EXP
+    tau_mode: int = I.TAU_CONST
+    tau: float = 0.1
+    inflow: tuple = (1.0, 0.0, 0.0, 0.0, 1.0)
+    t_wall: float = 1.0
+    fields: str = "sine_rho"
+    field_args: dict = dataclasses.field(default_factory=dict)
+    solid: object = None
+    cfl: float = 0.5
+
+
+def prim_for(case, input_index):
+    x = I.leaf_centres(case.forest)[input_index]
+    return I.fields(case.fields, x, **case.field_args)
+
+
+def oracle_run(case, steps):
+    om = O.Mesh(case.forest, case.solid)
+    t = om.tables()
+    p = O.make_params((case.nv,) * 3, (-case.vmax,) * 3, (case.vmax,) * 3, scheme=case.scheme,
+                      collision=case.collision, tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow,
+                      t_wall=case.t_wall)
+    s = O.Solver(om, p)
+    s.init_maxwellian(prim_for(case, t["input"]))
+    dt = s.dt_cfl(case.cfl)
+    rc = s.step(dt, steps)
+    return dict(f=s.get_f(), mom=s.moments(), dt=dt, rc=rc, input=t["input"], sums=s.global_sums())
+
+
+def gpu_solver(case, precision):
+    dm = D.Mesh(case.forest, case.solid)
+    t = dm.tables()
+    p = D.make_params(case.nv, case.vmax, precision=precision, scheme=case.scheme, collision=case.collision,
+                      tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow, t_wall=case.t_wall)
+    s = D.Solver(dm, p)
+    s.init_maxwellian(prim_for(case, t["input"]))
+    return dm, s
+
+
+def gpu_run(case, steps, precision):
+    import torch
+    dm, s = gpu_solver(case, precision)
+    dt = s.dt(case.cfl)
+    s.step(steps, dt=dt)
+    torch.cuda.synchronize()
+    f = s.f_canonical().double().cpu().numpy()
+    mom = s.moments().cpu().numpy()
+    rc, sums, bad, nsteps = s.check()
+    return dict(f=f, mom=mom, dt=dt, rc=rc, sums=sums, mom_step=s.mom.cpu().numpy())
+
+
+def moment_errors(m, ref):
+    """per-component L-inf error over cells, divided by (max rho, max rho sqrt(max T), ..., max E)"""
+    rho = ref[0]
+    u = ref[1:4] / rho
+    T = (2 * ref[4] / rho - (u * u).sum(0)) / 3
+    su = rho.max() * math.sqrt(T.max())
+    scale = np.array([rho.max(), su, su, su, ref[4].max()])
+    return np.abs(m - ref).max(axis=1) / scale

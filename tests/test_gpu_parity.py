@@ -1,0 +1,139 @@
+"""Parity of the HIP path (called through the C interface) with the FP64
+oracle on the same seeded inputs: FP64 within 1e-12 relative, FP32 storage
+with FP64 sums within 2e-5 relative L-inf on the moments after 20 steps."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+from tests.gpu_common import Case, balanced, gpu_run, gpu_solver, moment_errors, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+def _uniform16_v8():
+    w = I.workload("uniform16_v8_fp64")
+    return Case(w.forest, 8, 4.5, tau=0.1, fields="sine_rho", field_args={"a": 0.1})
+
+
+def _compare(case, steps, precision, tol, f_tol=None):
+    o = oracle_run(case, steps)
+    g = gpu_run(case, steps, precision)
+    assert o["rc"] == 0 and g["rc"] == 0
+    assert g["dt"] == pytest.approx(o["dt"], rel=1e-15)
+    err = moment_errors(g["mom"], o["mom"])
+    print("moment errors", err)
+    assert np.all(err <= tol), err
+    # the moments written by the step (post-transport, conserved by the collision)
+    err_step = moment_errors(g["mom_step"], o["mom"])
+    assert np.all(err_step <= max(tol, 1e-12)), err_step
+    if f_tol is not None:
+        ef = np.abs(g["f"] - o["f"]).max() / np.abs(o["f"]).max()
+        print("f error", ef)
+        assert ef <= f_tol
+    return o, g
+
+
+def test_uniform16_v8_fp64_20_steps():
+    _compare(_uniform16_v8(), 20, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_uniform16_v8_fp32_20_steps():
+    _compare(_uniform16_v8(), 20, D.PREC_FP32, FP32_TOL)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_octree_periodic_fp64(seed):
+    f = balanced(I.random_forest(seed, (2, 2, 2), 3, 0.2))
+    case = Case(f, 8, 4.5, tau=0.05, fields="sines", field_args={"seed": 100 + seed})
+    _compare(case, 10, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+@pytest.mark.parametrize("coll", [I.COLL_EULER, I.COLL_OFF])
+def test_octree_collision_modes_fp64(coll):
+    f = balanced(I.random_forest(2, (2, 2, 2), 2, 0.3))
+    case = Case(f, 8, 4.5, tau=0.2, collision=coll, fields="sines", field_args={"seed": 7})
+    _compare(case, 6, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_octree_inflow_outflow_wall_fp64():
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.WALL, I.OUTFLOW, I.OUTFLOW)
+    f = balanced(I.random_forest(3, (2, 2, 2), 3, 0.2, bc))
+    case = Case(f, 8, 6.0, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, 1.3, 0.1, 0.0, 1.1), t_wall=0.9,
+                fields="sines", field_args={"seed": 9})
+    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_sphere_solid_inflow_fp64():
+    f = balanced(I.sphere_refinement(base=(8, 8, 8), levels=2, radius=0.2))
+    sol = I.solid_flags(f, (0.5, 0.5, 0.5), 0.2, 2)
+    u_in = 2.0 * (5.0 / 3.0) ** 0.5
+    case = Case(f, 8, 6.0, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, u_in, 0.0, 0.0, 1.0), solid=sol,
+                fields="uniform", field_args={"rho": 1.0, "u": (u_in, 0.0, 0.0), "T": 1.0})
+    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+@pytest.mark.parametrize("nv,vmax", [(12, 6.0), (16, 6.0), (24, 6.0)])
+def test_octree_sod_hard_sphere(nv, vmax):
+    """the paper-scale construction (roots refined once at random, Sod-like jump,
+    tau from Kn) on 4^3 roots: FP64 to 1e-12, FP32 to 2e-5 after 20 steps"""
+    f = I.random_root_refinement((4, 4, 4), 0.4, 3)
+    case = Case(f, nv, vmax, tau_mode=I.TAU_HS, tau=0.01, fields="sod_x")
+    o, g = _compare(case, 20, D.PREC_FP32, FP32_TOL)
+    g64 = gpu_run(case, 20, D.PREC_FP64)
+    err = moment_errors(g64["mom"], o["mom"])
+    assert np.all(err <= FP64_TOL), err
+    ef = np.abs(g64["f"] - o["f"]).max() / np.abs(o["f"]).max()
+    assert ef <= FP64_TOL
+
+
+def test_stationary_maxwellian_and_conservation():
+    import torch
+    f = balanced(I.random_forest(4, (2, 2, 2), 3, 0.2))
+    case = Case(f, 8, 4.5, fields="uniform", field_args={"rho": 1.1, "u": (0.2, -0.1, 0.3), "T": 0.9})
+    dm, s = gpu_solver(case, D.PREC_FP64)
+    f0 = s.f_canonical().cpu().numpy()
+    s.step(20, cfl=0.5)
+    f1 = s.f_canonical().cpu().numpy()
+    assert np.abs(f1 - f0).max() <= 1e-14 * np.abs(f0).max()
+    # a non-uniform state on a periodic octree: global sums conserved
+    case2 = Case(f, 8, 4.5, tau=0.05, fields="sines", field_args={"seed": 3})
+    dm, s = gpu_solver(case2, D.PREC_FP64)
+    rc, g0, _, _ = s.check()
+    s.step(10, cfl=0.5)
+    rc, g1, bad, n = s.check()
+    assert rc == 0 and not bad and n == 10
+    assert np.all(np.abs(g1 - g0) <= 1e-13 * np.abs(g0).max())
+    torch.cuda.synchronize()
+
+
+def test_deterministic_bitwise():
+    f = balanced(I.random_forest(5, (2, 2, 2), 3, 0.2))
+    case = Case(f, 16, 6.0, tau_mode=I.TAU_HS, tau=0.02, fields="sines", field_args={"seed": 5})
+    a = gpu_run(case, 5, D.PREC_FP32)
+    b = gpu_run(case, 5, D.PREC_FP32)
+    assert np.array_equal(a["f"], b["f"])
+    assert np.array_equal(a["mom"], b["mom"])
+
+
+def test_canonical_roundtrip_and_nonphysical_flag():
+    import torch
+    f = I.uniform_forest((1, 1, 1), 2)
+    case = Case(f, 8, 4.5, fields="uniform")
+    dm, s = gpu_solver(case, D.PREC_FP32)
+    rng = np.random.default_rng(0)
+    x = rng.random((s.n, s.nv)).astype(np.float32)
+    s.set_f_canonical(x)
+    back = s.f_canonical().cpu().numpy()
+    assert np.array_equal(back, x)
+    x[5] = -1.0
+    s.set_f_canonical(x)
+    s.step(1, cfl=0.5)
+    rc, sums, bad, n = s.check()
+    assert rc == D.ERR_NONPHYSICAL and bad
+    torch.cuda.synchronize()

@@ -1,0 +1,123 @@
+"""Host-side checks of libdvm.so that need no GPU: the library loads and
+exports every declared entry point; its linear-octree mesh builder agrees bit
+for bit with the oracle's pointer octree; argument errors come back as status
+codes."""
+import dataclasses
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(dvm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_exports_every_declared_symbol():
+    L = D.lib()
+    names = declared_symbols()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(D.EXPORTED) <= set(names)
+
+
+def balanced_both(forest):
+    lo, io = O.balance(forest)
+    ld, id_ = D.balance(forest)
+    return (lo, io), (ld, id_)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("periodic", [True, False])
+def test_balance_bit_exact_vs_oracle(seed, periodic):
+    bc = (I.PERIODIC,) * 6 if periodic else (I.OUTFLOW,) * 6
+    f = I.random_forest(seed, (2, 3, 2), 3, 0.2, bc)
+    (lo, io), (ld, id_) = balanced_both(f)
+    assert np.array_equal(lo, ld)
+    assert np.array_equal(io, id_)
+
+
+def _compare_tables(f, solid=None):
+    om = O.Mesh(f, solid)
+    dm = D.Mesh(f, solid)
+    ot, dt = om.tables(), dm.tables()
+    assert om.n_cells == dm.n_cells
+    assert np.array_equal(ot["input"], dt["input"])
+    assert np.array_equal(ot["key"], dt["key"])
+    assert np.array_equal(ot["type"], dt["type"])
+    assert np.array_equal(ot["nbr"], dt["nbr"])
+    return dm
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("bc", [(I.PERIODIC,) * 6, (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)])
+def test_tables_bit_exact_vs_oracle(seed, bc):
+    f = I.random_forest(seed, (2, 2, 3), 3, 0.2, bc)
+    lev, ijk = D.balance(f)
+    _compare_tables(dataclasses.replace(f, level=lev, ijk=ijk))
+
+
+def test_tables_bit_exact_sphere_with_solid():
+    f = I.sphere_refinement(base=(8, 8, 8), levels=2, radius=0.2)
+    lev, ijk = D.balance(f)
+    fb = dataclasses.replace(f, level=lev, ijk=ijk)
+    sol = I.solid_flags(fb, (0.5, 0.5, 0.5), 0.2, 2)
+    dm = _compare_tables(fb, sol)
+    assert dm.n_faces[D.ERR_ARG + 6] >= 0  # smoke
+    assert dm.n_cells == fb.n - int(sol.sum())
+
+
+def test_tables_bit_exact_random_roots_16():
+    f = I.random_root_refinement((16, 16, 16), 0.4, 3, h0=1 / 16)
+    _compare_tables(f)
+
+
+def test_argument_errors():
+    f = I.random_forest(0, (2, 2, 2), 3, 0.3)
+    with pytest.raises(D.DvmError) as e:
+        D.Mesh(f)
+    assert e.value.code == D.ERR_UNBALANCED
+    g = I.uniform_forest((2, 2, 2), 1)
+    with pytest.raises(D.DvmError) as e:
+        D.Mesh(dataclasses.replace(g, level=g.level[1:], ijk=g.ijk[1:]))
+    assert e.value.code == D.ERR_NOT_PARTITION
+    dup = dataclasses.replace(g, level=np.concatenate([g.level, g.level[:1]]), ijk=np.concatenate([g.ijk, g.ijk[:1]]))
+    with pytest.raises(D.DvmError) as e:
+        D.Mesh(dup)
+    assert e.value.code == D.ERR_NOT_PARTITION
+    with pytest.raises(D.DvmError) as e:
+        D.Mesh(dataclasses.replace(g, bc=(I.PERIODIC, I.OUTFLOW) + (I.PERIODIC,) * 4))
+    assert e.value.code == D.ERR_ARG
+
+
+def test_solver_argument_errors_host_only():
+    m = D.Mesh(I.uniform_forest((1, 1, 1), 2))
+    import ctypes as C
+    h = C.c_void_p()
+    for p, code in [(D.make_params(7, 4.5), D.ERR_UNSUPPORTED), (D.make_params(10, 4.5), D.ERR_UNSUPPORTED),
+                    (D.make_params(8, -1.0), D.ERR_ARG), (D.make_params(8, 4.5, tau_or_kn=0.0), D.ERR_ARG)]:
+        assert D.lib().dvm_create_solver(m.h, C.byref(p), C.byref(h)) == code
+    p = D.make_params(8, 4.5)
+    assert D.lib().dvm_create_solver(m.h, C.byref(p), C.byref(h)) == D.OK
+    sz = D.Sizes()
+    assert D.lib().dvm_buffer_sizes(h, C.byref(sz)) == D.OK
+    assert sz.n_cells == 64 and sz.nv_total == 512 and sz.f_bytes == 64 * 512 * 4
+    # step before bind/upload is refused before any device call
+    assert D.lib().dvm_step(h, 1, 0.0, 0.5, None) == D.ERR_WORKSPACE
+    dt = C.c_double()
+    assert D.lib().dvm_dt(h, C.c_double(0.5), C.byref(dt)) == D.OK
+    assert dt.value == 0.5 * 0.25 / (3 * 3.9375)
+    D.lib().dvm_destroy_solver(h)
