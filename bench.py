@@ -62,6 +62,9 @@ def gpu_bench(args):
     p = D.make_params(w.nv[0], w.vhi[0], precision=prec, scheme=w.scheme, collision=w.collision,
                       tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall)
     s = D.Solver(mesh, p)
+    if args.shape:
+        T, W, G, NT = (int(x) for x in args.shape.split(","))
+        s.set_shape(T, W, G, NT)
     s.init_maxwellian(prim)
     del prim
     dt = s.dt(w.cfl)
@@ -108,6 +111,27 @@ def gpu_bench(args):
                 rc=rc, drift=drift, g0=g0, w=w, fbytes=fbytes, dt=dt)
 
 
+def copy_calibration(gb):
+    """A plain device-to-device copy of known size: its HBM counters give the
+    scale factor between counter units and bytes."""
+    import torch
+    n = int(gb * 1e9) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"[bench] copy calibration: {4 * n / 1e9:.2f} GB read + write in {ms:.3f} ms = {8 * n / ms / 1e6:.0f} GB/s")
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(args):
     """FP64 oracle on the host cores: the same construction on 16^3 roots."""
     from oracle import oracle as O
@@ -148,11 +172,16 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shape", default="", help="threads,wpe,xcd_group,nt_store of the step kernel")
+    ap.add_argument("--copy-calibration-gb", type=float, default=0.0,
+                    help="also run a plain device copy of this many GB (read + write), for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration_gb > 0:
+        copy_calibration(args.copy_calibration_gb)
     r = gpu_bench(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     w = r["w"]

@@ -224,6 +224,20 @@ int dvm_moments(dvm_solver *s, double *out, void *stream);
  */
 int dvm_check(dvm_solver *s, void *stream, dvm_diag *out);
 
+/*
+ * Step-kernel shapes (autotuning).  A shape is (threads per workgroup, waves
+ * per EU variant); each solver also chooses an XCD cell grouping (runs of
+ * consecutive Morton cells kept on one XCD's L2) and plain or non-temporal
+ * stores of the new state.  dvm_tune_shapes lists the shapes compiled for the
+ * solver's velocity grid (at most cap; *n the total).  dvm_tune_set returns
+ * DVM_ERR_UNSUPPORTED for a shape that does not exist, DVM_ERR_ARG for
+ * xcd_group < 1.  The choice changes speed only: every shape computes the
+ * same step (bitwise, for a given grouping of the reductions per workgroup).
+ */
+int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t cap, int32_t *n);
+int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group, int32_t nt_store);
+int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store);
+
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);
 int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_internal, void *stream);

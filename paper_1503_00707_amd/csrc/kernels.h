@@ -32,7 +32,7 @@ struct StepArgs {
     int collision;           // DVM_COLL_*
     int tau_mode;            // DVM_TAU_*
     double tau_or_kn;
-    int xcd_group;           // consecutive cells kept on one XCD (>= 1)
+    int xcd_log2;            // runs of 2^xcd_log2 consecutive cells kept on one XCD
 };
 
 struct InitArgs {
@@ -48,7 +48,9 @@ struct InitArgs {
 // Kernel-configuration choice for one (precision, N) pair.
 struct StepConfig {
     int threads;     // workgroup size
-    int xcd_group;
+    int xcd_group;   // consecutive cells kept on one XCD
+    int nt_store;    // non-temporal stores of the new state
+    int wpe;         // waves-per-EU variant (0: the first listed for this shape)
 };
 
 // All return hipError_t of the launch (hipErrorInvalidValue: no kernel for N).
@@ -60,7 +62,18 @@ hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n
                               int n_part, double *out, hipStream_t st);
 hipError_t launch_to_canonical(bool fp64, bool to_canon, const void *src, void *dst, int64_t n, int nh,
                                hipStream_t st);
-bool have_kernel(bool fp64, int nh, int threads);
+bool have_kernel(int nh, int threads, int wpe);
+int list_kernels(int nh, int *threads, int *wpe, int cap);
 int default_threads(bool fp64, int nh);
+
+// per-precision instantiations (kernels_f32.hip, kernels_f64.hip)
+#define DVM_DECLARE_PREC(SUF)                                                                            \
+    hipError_t launch_step_##SUF(const StepArgs &a, const StepConfig &cfg, hipStream_t st);              \
+    hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
+    hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
+    hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);
+DVM_DECLARE_PREC(f32)
+DVM_DECLARE_PREC(f64)
+#undef DVM_DECLARE_PREC
 
 }  // namespace dvm

@@ -94,8 +94,17 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         s->g.dv[b] = 2.0 * p->vmax[b] / p->nv;
         s->g.w *= s->g.dv[b];
     }
+    // measured defaults per (precision, N); dvm_tune_set overrides them
     s->cfg.threads = thr;
     s->cfg.xcd_group = 1;
+    s->cfg.nt_store = 0;
+    s->cfg.wpe = 0;
+    if (nh == 12 && !fp64) {
+        s->cfg.threads = 192;
+        s->cfg.wpe = 31;
+        s->cfg.xcd_group = 8;
+        s->cfg.nt_store = 1;
+    }
     s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
     s->has_wall = m->n_faces[DVM_FACE_WALL] > 0;
     const size_t fs = fp64 ? 8 : 4;
@@ -232,7 +241,8 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     a.collision = s->p.collision;
     a.tau_mode = s->p.tau_mode;
     a.tau_or_kn = s->p.tau_or_kn;
-    a.xcd_group = s->cfg.xcd_group;
+    a.xcd_log2 = 0;
+    while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
     hipStream_t st = S(stream);
     for (int it = 0; it < n_steps; ++it) {
         a.f_in = s->f[s->cur];
@@ -306,6 +316,43 @@ int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_inter
     if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
     hipError_t e = launch_to_canonical(s->fp64, false, f_canon, f_internal, s->n, s->nh, S(stream));
     if (e != hipSuccess) return hip_fail(e, "from_canonical");
+    return DVM_OK;
+}
+
+int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t cap, int32_t *n) {
+    clear_error();
+    if (!s || !n || (cap > 0 && (!threads || !wpe))) return fail(DVM_ERR_ARG, "null argument");
+    int t[64], w[64];
+    const int total = list_kernels(s->nh, t, w, 64);
+    for (int k = 0; k < total && k < cap && k < 64; ++k) {
+        threads[k] = t[k];
+        wpe[k] = w[k];
+    }
+    *n = total;
+    return DVM_OK;
+}
+
+int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group, int32_t nt_store) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    if (xcd_group < 1 || xcd_group > 4096 || (xcd_group & (xcd_group - 1)))
+        return fail(DVM_ERR_ARG, "xcd_group must be a power of two in [1, 4096]");
+    if (!have_kernel(s->nh, threads, wpe))
+        return fail(DVM_ERR_UNSUPPORTED, "no step kernel with %d threads, wpe %d for N = %d", threads, wpe, 2 * s->nh);
+    s->cfg.threads = threads;
+    s->cfg.wpe = wpe;
+    s->cfg.xcd_group = xcd_group;
+    s->cfg.nt_store = nt_store != 0;
+    return DVM_OK;
+}
+
+int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store) {
+    clear_error();
+    if (!s || !threads || !wpe || !xcd_group || !nt_store) return fail(DVM_ERR_ARG, "null argument");
+    *threads = s->cfg.threads;
+    *wpe = s->cfg.wpe;
+    *xcd_group = s->cfg.xcd_group;
+    *nt_store = s->cfg.nt_store;
     return DVM_OK;
 }
 

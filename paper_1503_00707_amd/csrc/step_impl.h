@@ -1,0 +1,733 @@
+// step_impl.h -- device templates of the DVM-BGK step, instantiated per
+// storage precision in kernels_f32.hip / kernels_f64.hip.
+//
+// Layout.  f is [cell][velocity] with the velocity index innermost; the 8
+// velocity sign groups ("octants") are contiguous blocks of B = NH^3 nodes,
+// (-,-,-) first and the z sign fastest (section 3.1, step 1); inside an
+// octant, slot s = (ax*NH + ay)*NH + az has |xi_b| = (a_b + 1/2) dv_b.  A
+// workgroup owns one cell: thread t handles slots t, t+T, ... in every octant,
+// so (a) the |xi| of a thread's slots are the same in all 8 octants and only
+// the signs change, (b) within one octant all lanes read the same upwind
+// neighbour row: the upwind choice is a compile-time function of the octant
+// and the row pointer is workgroup-uniform, and 64 lanes read 256 contiguous
+// bytes of it.
+//
+// One step per cell, fused into one pass over HBM (read f once, write f once):
+//   transport   eq. (2) in flux form, f* = f - dt/h sum_b |xi_b| (f - f_up,b);
+//               f_up is the upwind neighbour (SAME/COARSER), the mean of the
+//               four finer neighbours (FINER: 4 sub-faces of area (h/2)^2), or
+//               a ghost value (inflow Maxwellian, own value at an outflow face,
+//               diffuse-wall re-emission).  Cells with only single-row faces
+//               take a branch-free path whose neighbour loads are all
+//               independent of each other (the compiler hoists them).
+//   moments     FP64 sums w sum (1, xi, |xi|^2/2) f*: the 8 octant values of a
+//               slot are combined by an FP64 Walsh butterfly, lane partials go
+//               through a wave butterfly and LDS (the O(log n) tree of
+//               section 3.2).
+//   Maxwellian  separable: one wave per axis computes its N exponentials and
+//               five 1D power sums; the 5x5 Gram system of eq. (6) in a
+//               centred basis is assembled from those 15 sums and solved in
+//               FP64 by every thread (no further barrier).
+//   relaxation  f' = e f* + (1-e) Mt, Mt = C g_x g_y g_z (P_x + P_y + P_z).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace dvm {
+namespace impl {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum K values over the workgroup; every thread receives the same totals in
+// a fixed combination order (deterministic).
+template <int T, int K>
+__device__ inline void block_sum(double (&v)[K], double *scratch) {
+    constexpr int NW = (T + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) scratch[wid * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += scratch[w * K + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; this gives each XCD
+// runs of 2^lg consecutive cells (a bijection on [0, nb); the tail that does
+// not fill a whole round keeps the identity).  Scalar: the result is uniform.
+__device__ inline uint32_t remap_cell(uint32_t b, uint32_t nb, int lg) {
+    const uint32_t chunk = 8u << lg;
+    const uint32_t full = nb - (nb & (chunk - 1));
+    uint32_t c = b;
+    if (b < full) {
+        const uint32_t xcd = b & 7u, local = b >> 3;
+        c = ((local >> lg) << (lg + 3)) + (xcd << lg) + (local & ((1u << lg) - 1));
+    }
+    return __builtin_amdgcn_readfirstlane(c);
+}
+
+// Row access through raw buffer instructions: one 4-SGPR descriptor per row
+// (base address, byte size), a per-lane 32-bit byte offset shared by every
+// row and a scalar byte offset per octant.  Out-of-range offsets read 0 and
+// drop writes instead of faulting.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (untyped) access
+constexpr int kAuxNT = 2;               // non-temporal cache policy
+
+// Every row base is workgroup-uniform by construction; readfirstlane states it
+// so that descriptors live in SGPRs (no per-lane waterfall around the loads).
+__device__ __forceinline__ Rsrc rsrc(const void *p, uint32_t bytes) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    void *u = reinterpret_cast<void *>((uint64_t(hi) << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, short(0), int(bytes), kRsrcWord3);
+}
+template <typename F>
+__device__ __forceinline__ F bld(Rsrc r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bld<float>(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+}
+template <typename F, int AUX>
+__device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, F v);
+template <>
+__device__ __forceinline__ void bst<float, 0>(Rsrc r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(voff), int(soff), 0);
+}
+template <>
+__device__ __forceinline__ void bst<float, kAuxNT>(Rsrc r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(voff), int(soff), kAuxNT);
+}
+template <>
+__device__ __forceinline__ void bst<double, 0>(Rsrc r, uint32_t voff, uint32_t soff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          int(voff), int(soff), 0);
+}
+template <>
+__device__ __forceinline__ void bst<double, kAuxNT>(Rsrc r, uint32_t voff, uint32_t soff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          int(voff), int(soff), kAuxNT);
+}
+
+// The 128-byte cell record, read once as dwords at kernel entry (uniform
+// scalar loads): words 0..23 the neighbour table, word 24 the kinds of faces
+// 0..3, word 25 the kinds of faces 4..5, the level and the flags.
+struct CellView {
+    uint32_t w[26];
+    const uint32_t *p;
+    __device__ __forceinline__ CellView(const DevCell *cells, int64_t c)
+        : p(reinterpret_cast<const uint32_t *>(cells + c)) {
+#pragma unroll
+        for (int k = 0; k < 26; ++k) w[k] = __builtin_amdgcn_readfirstlane(p[k]);
+    }
+    // runtime-indexed reads go to memory (scalar loads), not to a register array
+    __device__ __forceinline__ int type_rt(int f) const {
+        return (__builtin_amdgcn_readfirstlane(p[24 + (f >> 2)]) >> (8 * (f & 3))) & 0xff;
+    }
+    __device__ __forceinline__ int32_t nbr_rt(int f, int k) const {
+        return int32_t(__builtin_amdgcn_readfirstlane(p[4 * f + k]));
+    }
+    __device__ __forceinline__ int type(int f) const {
+        return f < 4 ? (w[24] >> (8 * f)) & 0xff : (w[25] >> (8 * (f - 4))) & 0xff;
+    }
+    __device__ __forceinline__ int level() const { return (w[25] >> 16) & 0xff; }
+    __device__ __forceinline__ int flags() const { return w[25] >> 24; }
+    __device__ __forceinline__ int32_t nbr(int f, int k) const { return int32_t(w[4 * f + k]); }
+};
+
+template <int NH>
+__device__ inline void slot_axes(int s, int &ax, int &ay, int &az) {
+    ax = s / (NH * NH);
+    ay = (s / NH) % NH;
+    az = s % NH;
+}
+
+// Thread -> velocity-slot map: thread t owns slots t + q*T, q < S, in every
+// octant, so one vector offset t*sizeof(F) addresses every row and the round
+// and octant offsets are scalar constants.  When T is a multiple of NH^2 the
+// thread's ay, az (hence |xi_y|, |xi_z|) are the same in every round and only
+// ax = t / NH^2 + q * T / NH^2 changes; otherwise the axes are decoded per
+// round.  Slots s >= B (padding of the last round) are not stored.
+template <int NH, int T>
+struct Lane {
+    static constexpr int B = NH * NH * NH;
+    static constexpr int S = (B + T - 1) / T;
+    static constexpr bool kQInv = S == 1 || T % (NH * NH) == 0;
+    __device__ __forceinline__ int slot(int q) const { return int(threadIdx.x) + q * T; }
+    __device__ __forceinline__ bool ok(int q) const { return S * T == B || slot(q) < B; }
+    __device__ __forceinline__ void axes(int q, int &ax, int &ay, int &az) const {
+        if (kQInv) {
+            const int t = threadIdx.x;
+            az = t % NH;
+            ay = (t / NH) % NH;
+            ax = t / (NH * NH) + q * (T / (NH * NH));
+        } else {
+            slot_axes<NH>(slot(q), ax, ay, az);
+        }
+    }
+    template <typename F>
+    static constexpr uint32_t soff(int o, int q) {
+        return uint32_t((o * B + q * T) * sizeof(F));
+    }
+};
+
+// The state values a thread keeps in registers during a step: [octant][round].
+template <typename F, int NH, int T>
+using Regs = F[8][Lane<NH, T>::S];
+
+template <typename F, int NH>
+struct MaxwellSmem {
+    static constexpr int N = 2 * NH;
+    double S[15];
+    double A[5][6];  // augmented Gram system
+    double d[5];
+    double C;
+    double g[3][N];
+    double c[3][N];
+    F tab[3][N][2];  // (G, P) per axis and node
+};
+
+// Entry (i, j) of the Gram matrix G'_ij = sum_i phi_i phi_j g_x g_y g_z dv^3
+// in the basis phi = (1, cx, cy, cz, |c|^2), from the 1D sums X, Y, Z (power
+// p of c at index p).
+__device__ inline double gram_entry(int i, int j, const double *X, const double *Y, const double *Z) {
+    const int ex = (i == 1) + (j == 1), ey = (i == 2) + (j == 2), ez = (i == 3) + (j == 3);
+    const int n4 = (i == 4) + (j == 4);
+    if (n4 == 0) return X[ex] * Y[ey] * Z[ez];
+    if (n4 == 1) return X[ex + 2] * Y[ey] * Z[ez] + X[ex] * Y[ey + 2] * Z[ez] + X[ex] * Y[ey] * Z[ez + 2];
+    return X[4] * Y[0] * Z[0] + X[0] * Y[4] * Z[0] + X[0] * Y[0] * Z[4] +
+           2.0 * (X[2] * Y[2] * Z[0] + X[2] * Y[0] * Z[2] + X[0] * Y[2] * Z[2]);
+}
+
+// Corrected discrete Maxwellian of (rho, u, T) as separable tables:
+//   Mt_i = C g_x g_y g_z (1 + d.phi_i),  phi = (1, cx, cy, cz, |c|^2),
+//   c = (xi - u)/sqrt(T), g = exp(-c^2/2), C = rho (2 pi T)^(-3/2).
+// d solves G d = r with G_ab = w sum_i phi_a phi_b M_i (the five conservation
+// equations of eq. 6 in a centred basis spanning the same polynomials) and
+// r = (rho, 0, 0, 0, 3 rho) - G[:,0], the phi-moments of the target minus
+// those of the raw Maxwellian.  Every entry of G is a product of 1D sums
+// S_b,p = dv_b sum_k c_k^p g_k, so the cost per cell is O(N), not O(N^3).
+// The 5x6 augmented system is eliminated Gauss-Jordan style by 30 lanes of
+// the first wave through LDS (one element per lane; G is symmetric positive
+// definite, so no pivoting).  tab[0] carries C * mfac, so that the table
+// product is mfac * Mt.
+template <typename F, int NH, int T>
+__device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, double mfac,
+                               const VelGrid &g) {
+    constexpr int N = 2 * NH;
+    constexpr int NW = (T + 63) / 64;
+    static_assert(N <= 64, "one wave per axis");
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int b = wid; b < 3; b += NW) {
+        double gk = 0.0, ck = 0.0;
+        if (lane < N) {
+            const double xi = (double(lane - NH) + 0.5) * g.dv[b];
+            ck = (xi - u[b]) / sqrt(Tt);
+            gk = exp(-0.5 * ck * ck);
+            sm.g[b][lane] = gk;
+            sm.c[b][lane] = ck;
+        }
+        double p[5];
+        p[0] = gk;
+#pragma unroll
+        for (int q = 1; q < 5; ++q) p[q] = p[q - 1] * ck;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) p[q] = wave_sum(p[q]);
+        if (lane == 0)
+            for (int q = 0; q < 5; ++q) sm.S[5 * b + q] = p[q] * g.dv[b];
+    }
+    __syncthreads();
+    if (wid == 0) {
+        const int i = lane / 6, j = lane % 6;
+        const bool el = lane < 30;
+        const double x2 = 6.283185307179586476925286766559 * Tt;
+        const double C = rho / (x2 * sqrt(x2));
+        if (el) {
+            double v;
+            if (j < 5) v = gram_entry(i, j, &sm.S[0], &sm.S[5], &sm.S[10]);
+            else {
+                const double t = (i == 0 ? 1.0 : i == 4 ? 3.0 : 0.0) * (rho / C);
+                v = t - gram_entry(i, 0, &sm.S[0], &sm.S[5], &sm.S[10]);
+            }
+            sm.A[i][j] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < 5; ++k) {
+            double nv = 0.0;
+            if (el && i != k) nv = sm.A[i][j] - sm.A[i][k] / sm.A[k][k] * sm.A[k][j];
+            __builtin_amdgcn_wave_barrier();
+            if (el && i != k) sm.A[i][j] = nv;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane < 5) sm.d[lane] = sm.A[lane][5] / sm.A[lane][lane];
+        if (lane == 0) sm.C = C;
+    }
+    __syncthreads();
+    for (int b = wid; b < 3; b += NW) {
+        if (lane < N) {
+            const double cc = sm.c[b][lane];
+            const double P = b == 0 ? 1.0 + sm.d[0] + sm.d[1] * cc + sm.d[4] * cc * cc
+                                    : sm.d[1 + b] * cc + sm.d[4] * cc * cc;
+            const double G = b == 0 ? sm.g[b][lane] * sm.C * mfac : sm.g[b][lane];
+            sm.tab[b][lane][0] = F(G);
+            sm.tab[b][lane][1] = F(P);
+        }
+    }
+    __syncthreads();
+}
+
+// Write f' = e*fs + M' for the slots of this thread, M' from the tables.
+template <typename F, int NH, int T, bool NT>
+__device__ inline void relax_store(const MaxwellSmem<F, NH> &sm, const Regs<F, NH, T> &fo, F e, Rsrc out) {
+    using L = Lane<NH, T>;
+    const L ln;
+    const uint32_t voff = threadIdx.x * sizeof(F);
+#pragma unroll
+    for (int q = 0; q < L::S; ++q) {
+        if (!ln.ok(q)) continue;
+        int a3[3];
+        ln.axes(q, a3[0], a3[1], a3[2]);
+        F G[3][2], P[3][2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            G[b][0] = sm.tab[b][NH - 1 - a3[b]][0];
+            G[b][1] = sm.tab[b][NH + a3[b]][0];
+            P[b][0] = sm.tab[b][NH - 1 - a3[b]][1];
+            P[b][1] = sm.tab[b][NH + a3[b]][1];
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o >> 2, oy = (o >> 1) & 1, oz = o & 1;
+            const F M = (G[0][ox] * G[1][oy]) * G[2][oz] * ((P[0][ox] + P[1][oy]) + P[2][oz]);
+            bst<F, NT ? kAuxNT : 0>(out, voff, L::template soff<F>(o, q), e * fo[o][q] + M);
+        }
+    }
+}
+
+// FP64 Walsh butterfly over the 8 octant values of one slot:
+// s0 = sum, sx/sy/sz = signed sums along each axis (o = ox*4 + oy*2 + oz).
+template <typename F, int S>
+__device__ inline void octant_sums(const F (&v)[8][S], int q, double &s0, double &sx, double &sy, double &sz) {
+    double d[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) d[o] = double(v[o][q]);
+    const double p0 = d[4] + d[0], m0 = d[4] - d[0];
+    const double p1 = d[5] + d[1], m1 = d[5] - d[1];
+    const double p2 = d[6] + d[2], m2 = d[6] - d[2];
+    const double p3 = d[7] + d[3], m3 = d[7] - d[3];
+    sx = (m0 + m1) + (m2 + m3);
+    const double q0 = p2 + p0, n0 = p2 - p0;
+    const double q1 = p3 + p1, n1 = p3 - p1;
+    sy = n0 + n1;
+    s0 = q1 + q0;
+    sz = q1 - q0;
+}
+
+template <typename F, int NH, int T>
+struct StepSmem {
+    static constexpr int NW = (T + 63) / 64;
+    double red[NW * 5];
+    double rho_w[6];
+    MaxwellSmem<F, NH> mx;
+};
+
+// Transport of the thread's slots; fo holds f on entry and f* on return.
+// Main pass: per octant the three upwind faces are compile-time constants and
+// every face is read through one row descriptor, so the loop has no branch
+// and its loads are independent (the compiler pipelines them).  FINER and
+// WALL faces are given an empty descriptor there (reads return 0); the
+// correction pass then adds nu * f_up for them, f_up the mean of the four
+// finer rows or rho_w times the wall Maxwellian.
+template <typename F, int NH, int T, bool OCT_FENCE>
+__device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &cell, const Rsrc (&R1)[6],
+                                          const F *fin, const StepArgs &a, const double *rho_w, double dth,
+                                          double (&m)[5]) {
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    constexpr int64_t NV = 8 * L::B;
+    constexpr uint32_t kRow = uint32_t(NV * sizeof(F));
+    const L ln;
+    const uint32_t voff = threadIdx.x * sizeof(F);
+    F nu[3][S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        int a3[3];
+        ln.axes(q, a3[0], a3[1], a3[2]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nu[b][q] = F(dth) * (F(a3[b]) + F(0.5)) * F(a.g.dv[b]);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        // a positive component enters through the low face, a negative one through the high face
+        const int fx = 0 + ((o >> 2) ? 0 : 1), fy = 2 + (((o >> 1) & 1) ? 0 : 1), fz = 4 + ((o & 1) ? 0 : 1);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint32_t so = L::template soff<F>(o, q);
+            const F v = fo[o][q];
+            const F ux = bld<F>(R1[fx], voff, so);
+            const F uy = bld<F>(R1[fy], voff, so);
+            const F uz = bld<F>(R1[fz], voff, so);
+            fo[o][q] = v - (nu[0][q] * (v - ux) + nu[1][q] * (v - uy) + nu[2][q] * (v - uz));
+        }
+        // bound the look-ahead of the scheduler to one octant: hoisting loads
+        // further only trades them for spills
+        if (OCT_FENCE) asm volatile("" ::: "memory");
+    }
+    // correction for FINER and WALL faces: a runtime loop over the faces (one
+    // face's loads in flight at a time), workgroup-uniform branches
+#pragma nounroll
+    for (int f = 0; f < 6; ++f) {
+        const int ty = cell.type_rt(f);
+        if (ty != DVM_FACE_FINER && ty != DVM_FACE_WALL) continue;
+        const int b = f >> 1, enter = (f & 1) ? 0 : 1;  // sign bit of the velocities entering through f
+        const bool finer = ty == DVM_FACE_FINER;
+        Rsrc r[4];
+        F sc;
+        if (finer) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[k] = rsrc(fin + int64_t(cell.nbr_rt(f, k)) * NV, kRow);
+            sc = F(0.25);
+        } else {
+            r[0] = r[1] = r[2] = r[3] = rsrc(a.wall_m1, kRow);
+            sc = F(rho_w[f]);
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
+            if (sg[b] != enter) continue;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const uint32_t so = L::template soff<F>(o, q);
+                F up = bld<F>(r[0], voff, so);
+                if (finer) up = (up + bld<F>(r[1], voff, so)) + (bld<F>(r[2], voff, so) + bld<F>(r[3], voff, so));
+                const F nub = b == 0 ? nu[0][q] : b == 1 ? nu[1][q] : nu[2][q];
+                fo[o][q] += nub * (sc * up);
+            }
+            asm volatile("" ::: "memory");
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        if (!ln.ok(q)) continue;
+        int a3[3];
+        ln.axes(q, a3[0], a3[1], a3[2]);
+        const double xa = (a3[0] + 0.5) * a.g.dv[0];
+        const double ya = (a3[1] + 0.5) * a.g.dv[1];
+        const double za = (a3[2] + 0.5) * a.g.dv[2];
+        double s0, sx, sy, sz;
+        octant_sums<F, S>(fo, q, s0, sx, sy, sz);
+        m[0] += s0;
+        m[1] += xa * sx;
+        m[2] += ya * sy;
+        m[3] += za * sz;
+        m[4] += 0.5 * (xa * xa + ya * ya + za * za) * s0;
+    }
+}
+
+// One fused step for one cell per workgroup.
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
+    constexpr int B = NH * NH * NH;
+    constexpr int64_t NV = 8 * B;
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    __shared__ StepSmem<F, NH, T> sm;
+
+    const int tid = threadIdx.x;
+    const L ln;
+    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
+    const CellView cell(a.cells, c);
+    const F *fin = static_cast<const F *>(a.f_in);
+    constexpr uint32_t kRow = uint32_t(NV * sizeof(F));
+    const Rsrc own = rsrc(fin + c * NV, kRow);
+    const double dth = a.dt / (a.h0 / double(1 << cell.level()));
+
+    // own values of every slot and octant, kept in registers for the step
+    F fo[8][S];
+    const uint32_t voff = tid * sizeof(F);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) fo[o][q] = bld<F>(own, voff, L::template soff<F>(o, q));
+
+    // diffuse walls: density of the re-emitted Maxwellian (zero net mass flux)
+    if (cell.flags() & 1) {
+        for (int f = 0; f < 6; ++f) {
+            if (cell.type(f) != DVM_FACE_WALL) continue;
+            const int axis = f >> 1, side = f & 1;
+            double v[1] = {0.0};
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (!ln.ok(q)) continue;
+                int a3[3];
+                ln.axes(q, a3[0], a3[1], a3[2]);
+                const double xa = (a3[axis] + 0.5) * a.g.dv[axis];
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const int sb = axis == 0 ? (o >> 2) : axis == 1 ? ((o >> 1) & 1) : (o & 1);
+                    if (sb == side) v[0] += xa * double(fo[o][q]);  // leaving through this face
+                }
+            }
+            block_sum<T, 1>(v, sm.red);
+            if (tid == 0) sm.rho_w[f] = v[0] / a.wall_den[f];
+        }
+        __syncthreads();
+    }
+
+    // one row descriptor per face for the main transport pass
+    Rsrc R1[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int ty = cell.type(f);
+        const F *row = fin + c * NV;  // OUTFLOW: zero gradient
+        uint32_t bytes = kRow;
+        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) row = fin + int64_t(cell.nbr(f, 0)) * NV;
+        else if (ty == DVM_FACE_INFLOW) row = static_cast<const F *>(a.ghost_in);
+        else if (ty == DVM_FACE_FINER || ty == DVM_FACE_WALL) bytes = 0;  // added by the correction pass
+        R1[f] = rsrc(row, bytes);
+    }
+
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    transport<F, NH, T, (FENCE != 0)>(fo, cell, R1, fin, a, sm.rho_w, dth, m);
+    block_sum<T, 5>(m, sm.red);
+
+    const double w = a.g.w;
+    const double rho = w * m[0];
+    const double u[3] = {w * m[1] / rho, w * m[2] / rho, w * m[3] / rho};
+    const double E = w * m[4];
+    const double Tt = (2.0 * E / rho - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
+    const bool bad = !(rho > 0.0) || !(Tt > 0.0);
+    if (tid == 0) {
+        const int64_t n = a.n_cells;
+        a.mom[c] = rho;
+        a.mom[n + c] = w * m[1];
+        a.mom[2 * n + c] = w * m[2];
+        a.mom[3 * n + c] = w * m[3];
+        a.mom[4 * n + c] = E;
+        if (bad) *a.flag = 1;
+    }
+    const Rsrc out = rsrc(static_cast<F *>(a.f_out) + c * NV, kRow);
+    if (bad || a.collision == DVM_COLL_OFF) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (!ln.ok(q)) continue;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) bst<F, 0>(out, voff, L::template soff<F>(o, q), fo[o][q]);
+        }
+        return;
+    }
+    const double tau = a.tau_mode == DVM_TAU_HS ? a.tau_or_kn / (rho * sqrt(Tt)) : a.tau_or_kn;
+    double e, mfac;
+    if (a.collision == DVM_COLL_EULER) {
+        e = 1.0 - a.dt / tau;
+        mfac = a.dt / tau;
+    } else {
+        e = exp(-a.dt / tau);
+        mfac = -expm1(-a.dt / tau);
+    }
+    maxwell_tables<F, NH, T>(sm.mx, rho, u, Tt, mfac, a.g);
+    relax_store<F, NH, T, NT>(sm.mx, fo, F(e), out);
+}
+
+// f := corrected Maxwellian of a prescribed state (init and ghost rows).
+template <typename F, int NH, int T>
+__global__ __launch_bounds__(T) void k_init(InitArgs a) {
+    constexpr int B = NH * NH * NH;
+    constexpr int64_t NV = 8 * B;
+    constexpr int S = Lane<NH, T>::S;
+    __shared__ MaxwellSmem<F, NH> sm;
+    const int64_t c = blockIdx.x;
+    double p[5];
+    for (int k = 0; k < 5; ++k) p[k] = a.prim ? a.prim[k * a.n + c] : a.prim0[k];
+    const double rho = p[0], u[3] = {p[1], p[2], p[3]}, Tt = p[4];
+    const Rsrc out = rsrc(static_cast<F *>(a.f_out) + c * NV, uint32_t(NV * sizeof(F)));
+    if (!(rho > 0.0) || !(Tt > 0.0)) {
+        if (threadIdx.x == 0) *a.flag = 1;
+        return;
+    }
+    if (threadIdx.x == 0 && a.mom) {
+        a.mom[c] = rho;
+        for (int b = 0; b < 3; ++b) a.mom[(1 + b) * a.n + c] = rho * u[b];
+        a.mom[4 * a.n + c] = 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + 1.5 * rho * Tt;
+    }
+    maxwell_tables<F, NH, T>(sm, rho, u, Tt, 1.0, a.g);
+    F zero[8][S];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) zero[o][q] = F(0);
+    relax_store<F, NH, T, false>(sm, zero, F(0), out);
+}
+
+// FP64 conserved moments of stored states.
+template <typename F, int NH, int T>
+__global__ __launch_bounds__(T) void k_moments(const F *f, double *out, int64_t n, VelGrid g) {
+    constexpr int B = NH * NH * NH;
+    constexpr int64_t NV = 8 * B;
+    constexpr int NW = (T + 63) / 64;
+    __shared__ double red[NW * 5];
+    const int64_t c = blockIdx.x;
+    const F *row = f + c * NV;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int s = threadIdx.x; s < B; s += T) {
+        int a3[3];
+        slot_axes<NH>(s, a3[0], a3[1], a3[2]);
+        const double xa = (a3[0] + 0.5) * g.dv[0], ya = (a3[1] + 0.5) * g.dv[1], za = (a3[2] + 0.5) * g.dv[2];
+        F v[8][1];
+        for (int o = 0; o < 8; ++o) v[o][0] = row[o * B + s];
+        double s0, sx, sy, sz;
+        octant_sums<F, 1>(v, 0, s0, sx, sy, sz);
+        m[0] += s0;
+        m[1] += xa * sx;
+        m[2] += ya * sy;
+        m[3] += za * sz;
+        m[4] += 0.5 * (xa * xa + ya * ya + za * za) * s0;
+    }
+    block_sum<T, 5>(m, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) out[k * n + c] = g.w * m[k];
+}
+
+// Wall denominators: sum over velocities entering the fluid through face f
+// (xi.n < 0, n the outward normal of the fluid cell) of |xi.n| M1.
+template <typename F, int NH>
+__global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelGrid g) {
+    constexpr int B = NH * NH * NH;
+    __shared__ double red[4 * 6];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = threadIdx.x; s < B; s += 256) {
+        int a3[3];
+        slot_axes<NH>(s, a3[0], a3[1], a3[2]);
+        for (int o = 0; o < 8; ++o) {
+            const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
+            const double val = double(m1[o * B + s]);
+            for (int f = 0; f < 6; ++f) {
+                const int axis = f >> 1, side = f & 1;
+                if (sg[axis] != side) v[f] += (a3[axis] + 0.5) * g.dv[axis] * val;
+            }
+        }
+    }
+    block_sum<256, 6>(v, red);
+    if (threadIdx.x == 0)
+        for (int f = 0; f < 6; ++f) den[f] = v[f];
+}
+
+// ---------------------------------------------------------------------------
+// configuration table: (NH, threads, waves per EU); every step kernel comes
+// with and without non-temporal stores
+// ---------------------------------------------------------------------------
+#define DVM_STEP_CONFIGS(X) \
+    X(2, 64, 4, 0)          \
+    X(4, 64, 5, 0)          \
+    X(6, 256, 6, 0)         \
+    X(8, 256, 5, 0)         \
+    X(8, 256, 5, 1)         \
+    X(8, 512, 4, 0)         \
+    X(12, 192, 3, 1)        \
+    X(12, 576, 3, 0)        \
+    X(12, 576, 5, 1)        \
+    X(12, 576, 7, 1)
+
+template <typename F>
+hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t st) {
+    const dim3 grid(unsigned(a.n_cells));
+#define X(NH, T, W, FN)                                                                       \
+    if (a.g.nh == NH && cfg.threads == T && (cfg.wpe == 0 || cfg.wpe == 10 * W + FN)) {        \
+        if (cfg.nt_store) hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true>), grid, dim3(T), 0, st, a);  \
+        else hipLaunchKernelGGL((k_step<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, a);    \
+        return hipGetLastError();                                                             \
+    }
+    DVM_STEP_CONFIGS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+inline int step_config_list(int nh, int *threads, int *wpe, int cap) {
+    int n = 0;
+#define X(NH, T, W, FN)                 \
+    if (nh == NH) {                     \
+        if (n < cap) {                  \
+            threads[n] = T;             \
+            wpe[n] = 10 * W + FN;       \
+        }                               \
+        ++n;                            \
+    }
+    DVM_STEP_CONFIGS(X)
+#undef X
+    return n;
+}
+
+inline bool step_config_exists(int nh, int threads, int wpe) {
+#define X(NH, T, W, FN) \
+    if (nh == NH && threads == T && (wpe == 0 || wpe == 10 * W + FN)) return true;
+    DVM_STEP_CONFIGS(X)
+#undef X
+    return false;
+}
+
+template <typename F>
+hipError_t init_dispatch(const InitArgs &a, hipStream_t st) {
+    const unsigned n = unsigned(a.n);
+    switch (a.g.nh) {
+    case 2: hipLaunchKernelGGL((k_init<F, 2, 64>), dim3(n), dim3(64), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_init<F, 4, 64>), dim3(n), dim3(64), 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_init<F, 6, 256>), dim3(n), dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_init<F, 8, 256>), dim3(n), dim3(256), 0, st, a); break;
+    case 12: hipLaunchKernelGGL((k_init<F, 12, 576>), dim3(n), dim3(576), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t moments_dispatch(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st) {
+    const F *p = static_cast<const F *>(f);
+    const unsigned nb = unsigned(n);
+    switch (g.nh) {
+    case 2: hipLaunchKernelGGL((k_moments<F, 2, 64>), dim3(nb), dim3(64), 0, st, p, out, n, g); break;
+    case 4: hipLaunchKernelGGL((k_moments<F, 4, 64>), dim3(nb), dim3(64), 0, st, p, out, n, g); break;
+    case 6: hipLaunchKernelGGL((k_moments<F, 6, 256>), dim3(nb), dim3(256), 0, st, p, out, n, g); break;
+    case 8: hipLaunchKernelGGL((k_moments<F, 8, 256>), dim3(nb), dim3(256), 0, st, p, out, n, g); break;
+    case 12: hipLaunchKernelGGL((k_moments<F, 12, 256>), dim3(nb), dim3(256), 0, st, p, out, n, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t wall_den_dispatch(const void *m1, double *den, const VelGrid &g, hipStream_t st) {
+    const F *p = static_cast<const F *>(m1);
+    switch (g.nh) {
+    case 2: hipLaunchKernelGGL((k_wall_den<F, 2>), dim3(1), dim3(256), 0, st, p, den, g); break;
+    case 4: hipLaunchKernelGGL((k_wall_den<F, 4>), dim3(1), dim3(256), 0, st, p, den, g); break;
+    case 6: hipLaunchKernelGGL((k_wall_den<F, 6>), dim3(1), dim3(256), 0, st, p, den, g); break;
+    case 8: hipLaunchKernelGGL((k_wall_den<F, 8>), dim3(1), dim3(256), 0, st, p, den, g); break;
+    case 12: hipLaunchKernelGGL((k_wall_den<F, 12>), dim3(1), dim3(256), 0, st, p, den, g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace impl
+}  // namespace dvm

@@ -26,7 +26,7 @@ EXPORTED = [
     "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
     "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
     "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
-    "dvm_destroy_solver",
+    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get",
 ]
 
 
@@ -91,6 +91,9 @@ def lib():
         L.dvm_check.argtypes = [P, P, C.POINTER(Diag)]
         L.dvm_f_to_canonical.argtypes = [P, P, P, P]
         L.dvm_f_from_canonical.argtypes = [P, P, P, P]
+        L.dvm_tune_shapes.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_int32)]
+        L.dvm_tune_set.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.dvm_tune_get.argtypes = [P, P, P, P, P]
         L.dvm_destroy_solver.argtypes = [P]
         L.dvm_destroy_solver.restype = None
         _LIB = L
@@ -254,6 +257,22 @@ class Solver:
         if rc not in (OK, ERR_NONPHYSICAL):
             _check(rc, "dvm_check")
         return rc, np.array(d.sums[:]), bool(d.nonphysical), int(d.steps)
+
+    def shapes(self):
+        n = C.c_int32(0)
+        t = np.zeros(64, np.int32)
+        w = np.zeros(64, np.int32)
+        _check(lib().dvm_tune_shapes(self.h, t.ctypes.data, w.ctypes.data, 64, C.byref(n)), "dvm_tune_shapes")
+        return [(int(t[k]), int(w[k])) for k in range(min(n.value, 64))]
+
+    def set_shape(self, threads, wpe, xcd_group=1, nt_store=0):
+        _check(lib().dvm_tune_set(self.h, int(threads), int(wpe), int(xcd_group), int(nt_store)), "dvm_tune_set")
+
+    def get_shape(self):
+        v = np.zeros(4, np.int32)
+        _check(lib().dvm_tune_get(self.h, v[0:].ctypes.data, v[1:].ctypes.data, v[2:].ctypes.data,
+                                  v[3:].ctypes.data), "dvm_tune_get")
+        return tuple(int(x) for x in v)
 
     def __del__(self):
         if getattr(self, "h", None):
