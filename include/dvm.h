@@ -226,7 +226,8 @@ int dvm_check(dvm_solver *s, void *stream, dvm_diag *out);
 
 /*
  * Step-kernel shapes (autotuning).  A shape is (threads per workgroup, waves
- * per EU variant); each solver also chooses an XCD cell grouping (runs of
+ * per EU variant) of the selected engine's main kernel (see dvm_tune_engine);
+ * each solver also chooses an XCD cell grouping (fused engine: runs of
  * consecutive Morton cells kept on one XCD's L2) and plain or non-temporal
  * stores of the new state.  dvm_tune_shapes lists the shapes compiled for the
  * solver's velocity grid (at most cap; *n the total).  dvm_tune_set returns
@@ -238,9 +239,26 @@ int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t
 int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group, int32_t nt_store);
 int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store);
 
+/*
+ * dvm_tune_engine -- choose how a step is executed (both compute the same
+ * Lie-split step: transport, eq. 2, then BGK relaxation to the eq. 6
+ * corrected Maxwellian):
+ *   0  fused (default): one workgroup per cell runs transport, moments,
+ *      Maxwellian and relaxation; the state buffer holds f;
+ *   1  deferred collision: one workgroup per (cell, velocity
+ *      octant) runs the transport of the relaxed state and stores f*; a small
+ *      per-cell pass then builds the relaxation record (corrected Maxwellian
+ *      tables, relaxation factor, wall densities) that the next transport
+ *      applies when it reads f*.  dvm_moments / dvm_f_to_canonical present f.
+ * engine < 0 only queries; *previous (may be NULL) receives the engine in use.
+ * The shapes listed by dvm_tune_shapes and set by dvm_tune_set are those of
+ * the selected engine.
+ */
+int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
+
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);
-int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_internal, void *stream);
+int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, void *stream);
 
 void dvm_destroy_solver(dvm_solver *s);
 

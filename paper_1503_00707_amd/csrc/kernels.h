@@ -66,12 +66,59 @@ bool have_kernel(int nh, int threads, int wpe);
 int list_kernels(int nh, int *threads, int *wpe, int cap);
 int default_threads(bool fp64, int nh);
 
+// Deferred-collision engine (lazy_impl.h).
+struct UnitArgsPub {
+    const void *f_in;
+    void *f_out;
+    const void *tab;
+    double *partials;
+    const DevCell *cells;
+    const void *ghost_in;
+    const void *wall_m1;
+    const void *null_rec;
+    int64_t n_cells;
+    double dt;
+    double h0;
+    VelGrid g;
+};
+struct TableArgsPub {
+    const double *partials;
+    void *tab;
+    double *mom;
+    const DevCell *cells;
+    const double *wall_den;
+    int *flag;
+    int64_t n_cells;
+    double dt;
+    VelGrid g;
+    int collide;
+    int collision;
+    int tau_mode;
+    double tau_or_kn;
+};
+hipError_t launch_unit(bool fp64, const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st);
+hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st);
+hipError_t launch_identity(bool fp64, void *tab, int64_t n, int nh, hipStream_t st);
+hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, void *dst, int64_t n, int nh,
+                                hipStream_t st);
+hipError_t launch_materialize(bool fp64, void *fstar, void *tab, int64_t n, int nh, hipStream_t st);
+hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, double w, hipStream_t st);
+int table_stride(int nh);
+bool have_unit_kernel(int nh, int threads, int wpe);
+int list_unit_kernels(int nh, int *threads, int *wpe, int cap);
+
 // per-precision instantiations (kernels_f32.hip, kernels_f64.hip)
 #define DVM_DECLARE_PREC(SUF)                                                                            \
     hipError_t launch_step_##SUF(const StepArgs &a, const StepConfig &cfg, hipStream_t st);              \
     hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
     hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
-    hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);
+    hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);              \
+    hipError_t launch_unit_##SUF(const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st); \
+    hipError_t launch_tables_##SUF(const TableArgsPub &a, hipStream_t st);                               \
+    hipError_t launch_identity_##SUF(void *tab, int64_t n, int nh, hipStream_t st);                      \
+    hipError_t launch_canon_relaxed_##SUF(const void *fstar, const void *tab, void *dst, int64_t n, int nh, \
+                                          hipStream_t st);                                               \
+    hipError_t launch_materialize_##SUF(void *fstar, void *tab, int64_t n, int nh, hipStream_t st);
 DVM_DECLARE_PREC(f32)
 DVM_DECLARE_PREC(f64)
 #undef DVM_DECLARE_PREC

@@ -2,7 +2,7 @@
 // precision dispatch of the launch interface.
 #include <hip/hip_runtime.h>
 
-#include "step_impl.h"
+#include "lazy_impl.h"
 
 namespace dvm {
 namespace {
@@ -82,6 +82,30 @@ hipError_t launch_moments(bool fp64, const void *f, double *out, int64_t n, cons
 hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid &g, hipStream_t st) {
     return fp64 ? launch_wall_den_f64(m1, den, g, st) : launch_wall_den_f32(m1, den, g, st);
 }
+
+hipError_t launch_unit(bool fp64, const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st) {
+    return fp64 ? launch_unit_f64(a, threads, wpe, transport, nt, st) : launch_unit_f32(a, threads, wpe, transport, nt, st);
+}
+hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st) {
+    return fp64 ? launch_tables_f64(a, st) : launch_tables_f32(a, st);
+}
+hipError_t launch_identity(bool fp64, void *tab, int64_t n, int nh, hipStream_t st) {
+    return fp64 ? launch_identity_f64(tab, n, nh, st) : launch_identity_f32(tab, n, nh, st);
+}
+hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, void *dst, int64_t n, int nh,
+                                hipStream_t st) {
+    return fp64 ? launch_canon_relaxed_f64(fstar, tab, dst, n, nh, st) : launch_canon_relaxed_f32(fstar, tab, dst, n, nh, st);
+}
+hipError_t launch_materialize(bool fp64, void *fstar, void *tab, int64_t n, int nh, hipStream_t st) {
+    return fp64 ? launch_materialize_f64(fstar, tab, n, nh, st) : launch_materialize_f32(fstar, tab, n, nh, st);
+}
+hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, double w, hipStream_t st) {
+    hipLaunchKernelGGL(impl::k_sum_partials<0>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, partials, out, n, w);
+    return hipGetLastError();
+}
+int table_stride(int nh) { return impl::tab_stride(nh); }
+bool have_unit_kernel(int nh, int threads, int wpe) { return impl::unit_config_exists(nh, threads, wpe); }
+int list_unit_kernels(int nh, int *threads, int *wpe, int cap) { return impl::unit_config_list(nh, threads, wpe, cap); }
 
 hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
                               int n_part, double *out, hipStream_t st) {

@@ -44,7 +44,16 @@ struct dvm_solver {
     bool uploaded = false;
     int64_t steps = 0;
     bool has_inflow = false, has_wall = false;
+    // deferred-collision engine
+    int engine = 0;              // 0: fused (stores f), 1: deferred collision (stores f* + records)
+    int unit_threads = 0, unit_wpe = 0, unit_nt = 1;
+    size_t off_tab = 0, off_lpart = 0, off_null = 0;
+    bool lazy_valid = false;     // records describe f[cur] read as f*
+    bool relax_pending = false;  // some record is not the identity
 
+    void *tab() const { return ws + off_tab; }
+    void *null_rec() const { return ws + off_null; }
+    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
     void *gin() const { return ws + off_gin; }
     void *m1() const { return ws + off_m1; }
     double *den() const { return reinterpret_cast<double *>(ws + off_den); }
@@ -54,6 +63,68 @@ struct dvm_solver {
 };
 
 static hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
+
+static UnitArgsPub unit_args(const dvm_solver *s, const void *fin, void *fout, double dt) {
+    UnitArgsPub u{};
+    u.f_in = fin;
+    u.f_out = fout;
+    u.tab = s->tab();
+    u.partials = s->lpart();
+    u.cells = s->tables;
+    u.ghost_in = s->gin();
+    u.wall_m1 = s->m1();
+    u.null_rec = s->null_rec();
+    u.n_cells = s->n;
+    u.dt = dt;
+    u.h0 = s->m->h0;
+    u.g = s->g;
+    return u;
+}
+
+static TableArgsPub table_args(const dvm_solver *s, int collide, double dt, double *mom) {
+    TableArgsPub t{};
+    t.partials = s->lpart();
+    t.tab = s->tab();
+    t.mom = mom;
+    t.cells = s->tables;
+    t.wall_den = s->den();
+    t.flag = s->flag();
+    t.n_cells = s->n;
+    t.dt = dt;
+    t.g = s->g;
+    t.collide = collide;
+    t.collision = s->p.collision;
+    t.tau_mode = s->p.tau_mode;
+    t.tau_or_kn = s->p.tau_or_kn;
+    return t;
+}
+
+// Make the records describe the current buffer as f* with no pending
+// relaxation: identity records, then the partial moments and the wall
+// densities of the current state.
+static hipError_t ensure_lazy(dvm_solver *s, hipStream_t st) {
+    if (s->lazy_valid) return hipSuccess;
+    hipError_t e = launch_identity(s->fp64, s->tab(), s->n, s->nh, st);
+    if (e != hipSuccess) return e;
+    UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
+    e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, false, false, st);
+    if (e != hipSuccess) return e;
+    TableArgsPub t = table_args(s, 0, 0.0, s->mom);
+    e = launch_tables(s->fp64, t, st);
+    if (e != hipSuccess) return e;
+    s->lazy_valid = true;
+    s->relax_pending = false;
+    return hipSuccess;
+}
+
+// Apply a pending relaxation in place so that the buffer holds f itself.
+static hipError_t ensure_plain(dvm_solver *s, hipStream_t st) {
+    if (!s->relax_pending) return hipSuccess;
+    hipError_t e = launch_materialize(s->fp64, s->f[s->cur], s->tab(), s->n, s->nh, st);
+    if (e != hipSuccess) return e;
+    s->relax_pending = false;
+    return hipSuccess;
+}
 
 static double max_speed_sum(const dvm_solver *s) {
     double r = 0.0;
@@ -118,7 +189,18 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->off_flag = o; o += 256;
     s->off_part = o; o += align256(size_t(kPartials) * 5 * 8);
     s->off_sums = o; o += 256;
+    s->off_tab = o;  o += align256(size_t(s->n) * size_t(table_stride(nh)) * fs);
+    s->off_lpart = o; o += align256(size_t(8) * size_t(s->n) * 5 * 8);
+    s->off_null = o; o += align256(size_t(table_stride(nh)) * fs);
     s->ws_bytes = o;
+    {
+        int t[16], w[16];
+        if (list_unit_kernels(nh, t, w, 16) > 0) {
+            s->unit_threads = t[0];
+            s->unit_wpe = w[0];
+        }
+        if (nh == 12) s->unit_wpe = 5;
+    }
     *out = s;
     return DVM_OK;
 }
@@ -185,6 +267,8 @@ int dvm_upload(dvm_solver *s, void *stream) {
         e = launch_wall_den(s->fp64, s->m1(), s->den(), s->g, st);
         if (e != hipSuccess) return hip_fail(e, "wall denominators");
     }
+    e = launch_identity(s->fp64, s->null_rec(), 1, s->nh, st);
+    if (e != hipSuccess) return hip_fail(e, "identity record");
     // the host table must stay valid until the copy has been consumed
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -206,6 +290,10 @@ int dvm_init_maxwellian(dvm_solver *s, const double *prim, void *stream) {
     a.f_out = s->f[0];
     hipError_t e = launch_init(s->fp64, a, S(stream));
     if (e != hipSuccess) return hip_fail(e, "init");
+    s->lazy_valid = false;
+    s->relax_pending = false;
+    e = ensure_lazy(s, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "init records");
     s->steps = 0;
     return DVM_OK;
 }
@@ -244,11 +332,24 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     a.xcd_log2 = 0;
     while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
     hipStream_t st = S(stream);
+    hipError_t e = s->engine == 1 ? ensure_lazy(s, st) : ensure_plain(s, st);
+    if (e != hipSuccess) return hip_fail(e, "state conversion");
     for (int it = 0; it < n_steps; ++it) {
-        a.f_in = s->f[s->cur];
-        a.f_out = s->f[s->cur ^ 1];
-        hipError_t e = launch_step(s->fp64, a, s->cfg, st);
-        if (e != hipSuccess) return hip_fail(e, "step");
+        if (s->engine == 1) {
+            UnitArgsPub u = unit_args(s, s->f[s->cur], s->f[s->cur ^ 1], dt);
+            e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, true, s->unit_nt != 0, st);
+            if (e != hipSuccess) return hip_fail(e, "transport units");
+            TableArgsPub t = table_args(s, 1, dt, s->mom);
+            e = launch_tables(s->fp64, t, st);
+            if (e != hipSuccess) return hip_fail(e, "collision records");
+            s->relax_pending = s->p.collision != DVM_COLL_OFF;
+        } else {
+            a.f_in = s->f[s->cur];
+            a.f_out = s->f[s->cur ^ 1];
+            e = launch_step(s->fp64, a, s->cfg, st);
+            if (e != hipSuccess) return hip_fail(e, "step");
+            s->lazy_valid = false;
+        }
         s->cur ^= 1;
         s->steps++;
         if (s->p.check_every > 0 && s->steps % s->p.check_every == 0) {
@@ -279,7 +380,14 @@ int dvm_moments(dvm_solver *s, double *out, void *stream) {
     clear_error();
     if (!s || !out) return fail(DVM_ERR_ARG, "null argument");
     if (!s->f[0]) return fail(DVM_ERR_WORKSPACE, "solver not bound");
-    hipError_t e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
+    hipError_t e;
+    if (s->relax_pending) {
+        UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
+        e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, false, false, S(stream));
+        if (e == hipSuccess) e = launch_sum_partials(s->lpart(), out, s->n, s->g.w, S(stream));
+    } else {
+        e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
+    }
     if (e != hipSuccess) return hip_fail(e, "moments");
     return DVM_OK;
 }
@@ -306,16 +414,27 @@ int dvm_check(dvm_solver *s, void *stream, dvm_diag *out) {
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream) {
     clear_error();
     if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
-    hipError_t e = launch_to_canonical(s->fp64, true, f_internal, f_canon, s->n, s->nh, S(stream));
+    hipError_t e;
+    if (s->relax_pending && f_internal == s->f[s->cur])
+        e = launch_canon_relaxed(s->fp64, f_internal, s->tab(), f_canon, s->n, s->nh, S(stream));
+    else
+        e = launch_to_canonical(s->fp64, true, f_internal, f_canon, s->n, s->nh, S(stream));
     if (e != hipSuccess) return hip_fail(e, "to_canonical");
     return DVM_OK;
 }
 
-int dvm_f_from_canonical(const dvm_solver *s, const void *f_canon, void *f_internal, void *stream) {
+int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, void *stream) {
     clear_error();
     if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
     hipError_t e = launch_to_canonical(s->fp64, false, f_canon, f_internal, s->n, s->nh, S(stream));
     if (e != hipSuccess) return hip_fail(e, "from_canonical");
+    if (f_internal == s->f[s->cur] && s->uploaded) {
+        // the buffer now holds f itself: fresh records, moments and wall densities
+        s->lazy_valid = false;
+        s->relax_pending = false;
+        e = ensure_lazy(s, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "records");
+    }
     return DVM_OK;
 }
 
@@ -323,7 +442,7 @@ int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t
     clear_error();
     if (!s || !n || (cap > 0 && (!threads || !wpe))) return fail(DVM_ERR_ARG, "null argument");
     int t[64], w[64];
-    const int total = list_kernels(s->nh, t, w, 64);
+    const int total = s->engine == 1 ? list_unit_kernels(s->nh, t, w, 64) : list_kernels(s->nh, t, w, 64);
     for (int k = 0; k < total && k < cap && k < 64; ++k) {
         threads[k] = t[k];
         wpe[k] = w[k];
@@ -337,6 +456,15 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
     if (!s) return fail(DVM_ERR_ARG, "null solver");
     if (xcd_group < 1 || xcd_group > 4096 || (xcd_group & (xcd_group - 1)))
         return fail(DVM_ERR_ARG, "xcd_group must be a power of two in [1, 4096]");
+    if (s->engine == 1) {
+        if (!have_unit_kernel(s->nh, threads, wpe))
+            return fail(DVM_ERR_UNSUPPORTED, "no unit kernel with %d threads, wpe %d for N = %d", threads, wpe, 2 * s->nh);
+        s->unit_threads = threads;
+        s->unit_wpe = wpe;
+        s->unit_nt = nt_store != 0;
+        s->cfg.xcd_group = xcd_group;
+        return DVM_OK;
+    }
     if (!have_kernel(s->nh, threads, wpe))
         return fail(DVM_ERR_UNSUPPORTED, "no step kernel with %d threads, wpe %d for N = %d", threads, wpe, 2 * s->nh);
     s->cfg.threads = threads;
@@ -349,10 +477,20 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
 int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store) {
     clear_error();
     if (!s || !threads || !wpe || !xcd_group || !nt_store) return fail(DVM_ERR_ARG, "null argument");
-    *threads = s->cfg.threads;
-    *wpe = s->cfg.wpe;
+    *threads = s->engine == 1 ? s->unit_threads : s->cfg.threads;
+    *wpe = s->engine == 1 ? s->unit_wpe : s->cfg.wpe;
     *xcd_group = s->cfg.xcd_group;
-    *nt_store = s->cfg.nt_store;
+    *nt_store = s->engine == 1 ? s->unit_nt : s->cfg.nt_store;
+    return DVM_OK;
+}
+
+int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    if (previous) *previous = s->engine;
+    if (engine < 0) return DVM_OK;  // query only
+    if (engine != 0 && engine != 1) return fail(DVM_ERR_ARG, "engine must be 0 (fused) or 1 (deferred collision)");
+    s->engine = engine;
     return DVM_OK;
 }
 

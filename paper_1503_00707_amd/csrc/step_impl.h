@@ -233,8 +233,7 @@ __device__ inline double gram_entry(int i, int j, const double *X, const double 
 // definite, so no pivoting).  tab[0] carries C * mfac, so that the table
 // product is mfac * Mt.
 template <typename F, int NH, int T>
-__device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, double mfac,
-                               const VelGrid &g) {
+__device__ void maxwell_solve(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, const VelGrid &g) {
     constexpr int N = 2 * NH;
     constexpr int NW = (T + 63) / 64;
     static_assert(N <= 64, "one wave per axis");
@@ -284,6 +283,15 @@ __device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double 
         if (lane == 0) sm.C = C;
     }
     __syncthreads();
+}
+
+// Fill the storage-precision tables from a solved Maxwellian (after
+// maxwell_solve): tab[0] carries C * mfac, so the table product is mfac * Mt.
+template <typename F, int NH, int T>
+__device__ void maxwell_fill(MaxwellSmem<F, NH> &sm, double mfac) {
+    constexpr int N = 2 * NH;
+    constexpr int NW = (T + 63) / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int b = wid; b < 3; b += NW) {
         if (lane < N) {
             const double cc = sm.c[b][lane];
@@ -295,6 +303,13 @@ __device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double 
         }
     }
     __syncthreads();
+}
+
+template <typename F, int NH, int T>
+__device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, double mfac,
+                               const VelGrid &g) {
+    maxwell_solve<F, NH, T>(sm, rho, u, Tt, g);
+    maxwell_fill<F, NH, T>(sm, mfac);
 }
 
 // Write f' = e*fs + M' for the slots of this thread, M' from the tables.

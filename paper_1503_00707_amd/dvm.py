@@ -26,7 +26,7 @@ EXPORTED = [
     "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
     "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
     "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
-    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get",
+    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine",
 ]
 
 
@@ -94,6 +94,7 @@ def lib():
         L.dvm_tune_shapes.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_tune_set.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dvm_tune_get.argtypes = [P, P, P, P, P]
+        L.dvm_tune_engine.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_destroy_solver.argtypes = [P]
         L.dvm_destroy_solver.restype = None
         _LIB = L
@@ -267,6 +268,12 @@ class Solver:
 
     def set_shape(self, threads, wpe, xcd_group=1, nt_store=0):
         _check(lib().dvm_tune_set(self.h, int(threads), int(wpe), int(xcd_group), int(nt_store)), "dvm_tune_set")
+
+    def engine(self, engine=-1):
+        """select the engine (0 fused, 1 deferred collision); returns the previous one"""
+        prev = C.c_int32(0)
+        _check(lib().dvm_tune_engine(self.h, int(engine), C.byref(prev)), "dvm_tune_engine")
+        return int(prev.value)
 
     def get_shape(self):
         v = np.zeros(4, np.int32)
