@@ -75,7 +75,8 @@ extern "C" {
 #define DVM_PREC_FP64 0         /* f stored and transported in FP64 */
 #define DVM_PREC_FP32 1         /* f in FP32; moments, Maxwellian, correction in FP64 */
 #define DVM_SCHEME_UPWIND1 0
-#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction */
+#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction (fused engine;
+                                   the workspace then also holds 3 face-value planes) */
 #define DVM_COLL_EXP 0          /* f' = Mt + (f* - Mt) exp(-dt/tau) */
 #define DVM_COLL_EULER 1        /* f' = f* + dt/tau (Mt - f*) */
 #define DVM_COLL_OFF 2          /* f' = f* */
@@ -120,7 +121,8 @@ typedef struct {
     size_t f_bytes;           /* one state buffer; two are bound (ping-pong) */
     size_t moments_bytes;     /* FP64 [5][n_cells] */
     size_t tables_bytes;      /* device mesh tables */
-    size_t ws_bytes;          /* ghost tables, flags, reduction partials */
+    size_t ws_bytes;          /* ghost tables, flags, reduction partials, records of the
+                                 deferred-collision engine, MUSCL face values */
     int64_t n_cells;
     int64_t nv_total;         /* N^3 */
 } dvm_sizes;
@@ -251,6 +253,7 @@ int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *x
  *      tables, relaxation factor, wall densities) that the next transport
  *      applies when it reads f*.  dvm_moments / dvm_f_to_canonical present f.
  * engine < 0 only queries; *previous (may be NULL) receives the engine in use.
+ * Engine 1 is first order only (DVM_ERR_UNSUPPORTED with DVM_SCHEME_MUSCL).
  * The shapes listed by dvm_tune_shapes and set by dvm_tune_set are those of
  * the selected engine.
  */

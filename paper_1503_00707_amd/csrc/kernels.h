@@ -33,6 +33,7 @@ struct StepArgs {
     int tau_mode;            // DVM_TAU_*
     double tau_or_kn;
     int xcd_log2;            // runs of 2^xcd_log2 consecutive cells kept on one XCD
+    const void *face;        // MUSCL face values [3][n_cells][NV] (NULL: first order)
 };
 
 struct InitArgs {
@@ -56,6 +57,7 @@ struct StepConfig {
 // All return hipError_t of the launch (hipErrorInvalidValue: no kernel for N).
 hipError_t launch_step(bool fp64, const StepArgs &a, const StepConfig &cfg, hipStream_t st);
 hipError_t launch_init(bool fp64, const InitArgs &a, hipStream_t st);
+hipError_t launch_face(bool fp64, const StepArgs &a, hipStream_t st);
 hipError_t launch_moments(bool fp64, const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st);
 hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid &g, hipStream_t st);
 hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
@@ -111,6 +113,7 @@ int list_unit_kernels(int nh, int *threads, int *wpe, int cap);
 #define DVM_DECLARE_PREC(SUF)                                                                            \
     hipError_t launch_step_##SUF(const StepArgs &a, const StepConfig &cfg, hipStream_t st);              \
     hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
+    hipError_t launch_face_##SUF(const StepArgs &a, hipStream_t st);                                     \
     hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
     hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);              \
     hipError_t launch_unit_##SUF(const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st); \

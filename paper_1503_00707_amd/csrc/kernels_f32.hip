@@ -7,6 +7,7 @@ hipError_t launch_step_f32(const StepArgs &a, const StepConfig &cfg, hipStream_t
     return impl::step_dispatch<float>(a, cfg, st);
 }
 hipError_t launch_init_f32(const InitArgs &a, hipStream_t st) { return impl::init_dispatch<float>(a, st); }
+hipError_t launch_face_f32(const StepArgs &a, hipStream_t st) { return impl::face_dispatch<float>(a, st); }
 hipError_t launch_moments_f32(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st) {
     return impl::moments_dispatch<float>(f, out, n, g, st);
 }

@@ -7,6 +7,7 @@ hipError_t launch_step_f64(const StepArgs &a, const StepConfig &cfg, hipStream_t
     return impl::step_dispatch<double>(a, cfg, st);
 }
 hipError_t launch_init_f64(const InitArgs &a, hipStream_t st) { return impl::init_dispatch<double>(a, st); }
+hipError_t launch_face_f64(const StepArgs &a, hipStream_t st) { return impl::face_dispatch<double>(a, st); }
 hipError_t launch_moments_f64(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st) {
     return impl::moments_dispatch<double>(f, out, n, g, st);
 }

@@ -71,6 +71,10 @@ hipError_t launch_step(bool fp64, const StepArgs &a, const StepConfig &cfg, hipS
     return fp64 ? launch_step_f64(a, cfg, st) : launch_step_f32(a, cfg, st);
 }
 
+hipError_t launch_face(bool fp64, const StepArgs &a, hipStream_t st) {
+    return fp64 ? launch_face_f64(a, st) : launch_face_f32(a, st);
+}
+
 hipError_t launch_init(bool fp64, const InitArgs &a, hipStream_t st) {
     return fp64 ? launch_init_f64(a, st) : launch_init_f32(a, st);
 }

@@ -99,7 +99,6 @@ __global__ __launch_bounds__(TL) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
     constexpr int B = NH * NH * NH;
     constexpr int P2 = NH * NH;
     constexpr int64_t NV = 8 * B;
-    constexpr int N = 2 * NH;
     using TLy = TabLayout<NH>;
     static_assert(P2 <= TL && TL % 64 == 0, "unit shape");
     constexpr uint32_t kRow = uint32_t(NV * sizeof(F));

@@ -36,6 +36,8 @@ struct dvm_solver {
     size_t f_bytes = 0, mom_bytes = 0, tab_bytes = 0, ws_bytes = 0;
     // workspace sections (byte offsets)
     size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
+    size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
+    bool muscl = false;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
     double *mom = nullptr;
@@ -55,6 +57,7 @@ struct dvm_solver {
     void *null_rec() const { return ws + off_null; }
     double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
     void *gin() const { return ws + off_gin; }
+    void *face() const { return muscl ? ws + off_face : nullptr; }
     void *m1() const { return ws + off_m1; }
     double *den() const { return reinterpret_cast<double *>(ws + off_den); }
     int *flag() const { return reinterpret_cast<int *>(ws + off_flag); }
@@ -143,7 +146,6 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         if (!(p->vmax[b] > 0)) return fail(DVM_ERR_ARG, "vmax[%d] must be > 0", b);
     if (p->precision != DVM_PREC_FP64 && p->precision != DVM_PREC_FP32) return fail(DVM_ERR_ARG, "bad precision");
     if (p->scheme != DVM_SCHEME_UPWIND1 && p->scheme != DVM_SCHEME_MUSCL) return fail(DVM_ERR_ARG, "bad scheme");
-    if (p->scheme == DVM_SCHEME_MUSCL) return fail(DVM_ERR_UNSUPPORTED, "MUSCL is not provided by the device path yet");
     if (p->collision < DVM_COLL_EXP || p->collision > DVM_COLL_OFF) return fail(DVM_ERR_ARG, "bad collision mode");
     if (p->tau_mode != DVM_TAU_CONST && p->tau_mode != DVM_TAU_HS) return fail(DVM_ERR_ARG, "bad tau mode");
     if (p->collision != DVM_COLL_OFF && !(p->tau_or_kn > 0)) return fail(DVM_ERR_ARG, "tau_or_kn must be > 0");
@@ -192,6 +194,9 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->off_tab = o;  o += align256(size_t(s->n) * size_t(table_stride(nh)) * fs);
     s->off_lpart = o; o += align256(size_t(8) * size_t(s->n) * 5 * 8);
     s->off_null = o; o += align256(size_t(table_stride(nh)) * fs);
+    s->muscl = p->scheme == DVM_SCHEME_MUSCL;
+    s->off_face = o;
+    if (s->muscl) o += 3 * s->f_bytes;
     s->ws_bytes = o;
     {
         int t[16], w[16];
@@ -331,6 +336,7 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     a.tau_or_kn = s->p.tau_or_kn;
     a.xcd_log2 = 0;
     while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
+    a.face = s->face();
     hipStream_t st = S(stream);
     hipError_t e = s->engine == 1 ? ensure_lazy(s, st) : ensure_plain(s, st);
     if (e != hipSuccess) return hip_fail(e, "state conversion");
@@ -346,6 +352,10 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
         } else {
             a.f_in = s->f[s->cur];
             a.f_out = s->f[s->cur ^ 1];
+            if (s->muscl) {
+                e = launch_face(s->fp64, a, st);
+                if (e != hipSuccess) return hip_fail(e, "MUSCL face values");
+            }
             e = launch_step(s->fp64, a, s->cfg, st);
             if (e != hipSuccess) return hip_fail(e, "step");
             s->lazy_valid = false;
@@ -490,6 +500,7 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous) {
     if (previous) *previous = s->engine;
     if (engine < 0) return DVM_OK;  // query only
     if (engine != 0 && engine != 1) return fail(DVM_ERR_ARG, "engine must be 0 (fused) or 1 (deferred collision)");
+    if (engine == 1 && s->muscl) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine is first order only");
     s->engine = engine;
     return DVM_OK;
 }

@@ -374,10 +374,10 @@ struct StepSmem {
 // WALL faces are given an empty descriptor there (reads return 0); the
 // correction pass then adds nu * f_up for them, f_up the mean of the four
 // finer rows or rho_w times the wall Maxwellian.
-template <typename F, int NH, int T, bool OCT_FENCE>
+template <typename F, int NH, int T, bool OCT_FENCE, bool MU>
 __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &cell, const Rsrc (&R1)[6],
-                                          const F *fin, const StepArgs &a, const double *rho_w, double dth,
-                                          double (&m)[5]) {
+                                          const Rsrc (&RD)[3], const F *fin, const F *face, const StepArgs &a,
+                                          const double *rho_w, double dth, double (&m)[5]) {
     using L = Lane<NH, T>;
     constexpr int S = L::S;
     constexpr int64_t NV = 8 * L::B;
@@ -403,7 +403,15 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
             const F ux = bld<F>(R1[fx], voff, so);
             const F uy = bld<F>(R1[fy], voff, so);
             const F uz = bld<F>(R1[fz], voff, so);
-            fo[o][q] = v - (nu[0][q] * (v - ux) + nu[1][q] * (v - uy) + nu[2][q] * (v - uz));
+            // the value leaving through the downwind face: the cell average
+            // (first order) or its MUSCL face value
+            F dx = v, dy = v, dz = v;
+            if (MU) {
+                dx = bld<F>(RD[0], voff, so);
+                dy = bld<F>(RD[1], voff, so);
+                dz = bld<F>(RD[2], voff, so);
+            }
+            fo[o][q] = v - (nu[0][q] * (dx - ux) + nu[1][q] * (dy - uy) + nu[2][q] * (dz - uz));
         }
         // bound the look-ahead of the scheduler to one octant: hoisting loads
         // further only trades them for spills
@@ -421,7 +429,10 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
         F sc;
         if (finer) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[k] = rsrc(fin + int64_t(cell.nbr_rt(f, k)) * NV, kRow);
+            for (int k = 0; k < 4; ++k) {
+                const int64_t nb = cell.nbr_rt(f, k);
+                r[k] = rsrc(MU ? face + (int64_t(b) * a.n_cells + nb) * NV : fin + nb * NV, kRow);
+            }
             sc = F(0.25);
         } else {
             r[0] = r[1] = r[2] = r[3] = rsrc(a.wall_m1, kRow);
@@ -461,7 +472,7 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
 }
 
 // One fused step for one cell per workgroup.
-template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
     constexpr int B = NH * NH * NH;
     constexpr int64_t NV = 8 * B;
@@ -510,21 +521,31 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
         __syncthreads();
     }
 
-    // one row descriptor per face for the main transport pass
+    // one row descriptor per face for the main transport pass: the upwind
+    // cell's average (first order) or its downwind MUSCL face value
+    const F *face = static_cast<const F *>(a.face);
     Rsrc R1[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
         const int ty = cell.type(f);
         const F *row = fin + c * NV;  // OUTFLOW: zero gradient
         uint32_t bytes = kRow;
-        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) row = fin + int64_t(cell.nbr(f, 0)) * NV;
-        else if (ty == DVM_FACE_INFLOW) row = static_cast<const F *>(a.ghost_in);
-        else if (ty == DVM_FACE_FINER || ty == DVM_FACE_WALL) bytes = 0;  // added by the correction pass
+        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) {
+            const int64_t nb = cell.nbr(f, 0);
+            row = MU ? face + ((f >> 1) * a.n_cells + nb) * NV : fin + nb * NV;
+        } else if (ty == DVM_FACE_INFLOW) {
+            row = static_cast<const F *>(a.ghost_in);
+        } else if (ty == DVM_FACE_FINER || ty == DVM_FACE_WALL) {
+            bytes = 0;  // added by the correction pass
+        }
         R1[f] = rsrc(row, bytes);
     }
+    Rsrc RD[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) RD[b] = rsrc(MU ? face + (b * a.n_cells + c) * NV : fin, MU ? kRow : 0u);
 
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    transport<F, NH, T, (FENCE != 0)>(fo, cell, R1, fin, a, sm.rho_w, dth, m);
+    transport<F, NH, T, (FENCE != 0), MU>(fo, cell, R1, RD, fin, face, a, sm.rho_w, dth, m);
     block_sum<T, 5>(m, sm.red);
 
     const double w = a.g.w;
@@ -563,6 +584,75 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     }
     maxwell_tables<F, NH, T>(sm.mx, rho, u, Tt, mfac, a.g);
     relax_store<F, NH, T, NT>(sm.mx, fo, F(e), out);
+}
+
+// MUSCL-minmod face values of the state a.f_in, three planes [3][n][NV] at
+// a.face (the paper is silent on the reconstruction; the reading: per cell,
+// axis b and velocity, sigma = minmod((f - fm)/dm, (fp - f)/dp) with fm, fp
+// the low- and high-side face-neighbour values -- the neighbour's average
+// (SAME, COARSER), the mean of the four finer leaves (FINER), the inflow
+// ghost (INFLOW) or the cell's own value (OUTFLOW) -- and dm, dp the centre
+// distances h, 3h/4 (FINER), 3h/2 (COARSER); sigma = 0 in a cell that touches
+// a wall).  Plane b holds the value at the face the velocity leaves through,
+//   D_b = f + sgn(xi_b) (h/2) sigma_b,
+// which is both the cell's outgoing value and the value its downwind
+// neighbour receives through that face.
+template <typename F, int NH>
+__global__ __launch_bounds__(256) void k_face(StepArgs a) {
+    constexpr int B = NH * NH * NH;
+    constexpr int64_t NV = 8 * B;
+    const int64_t c = blockIdx.x;
+    const CellView cell(a.cells, c);
+    const F *fin = static_cast<const F *>(a.f_in);
+    F *face = static_cast<F *>(const_cast<void *>(a.face));
+    const F *own = fin + c * NV;
+    const double h = a.h0 / double(1 << cell.level());
+    const bool wall = cell.flags() & 1;
+    // per face: up to four source rows, their count and the centre distance
+    const F *src[6][4];
+    int cnt[6];
+    F dist[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int ty = cell.type(f);
+        cnt[f] = 1;
+        src[f][0] = src[f][1] = src[f][2] = src[f][3] = own;  // OUTFLOW (and WALL: unused)
+        dist[f] = F(h);
+        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) {
+            src[f][0] = fin + int64_t(cell.nbr(f, 0)) * NV;
+            if (ty == DVM_FACE_COARSER) dist[f] = F(1.5 * h);
+        } else if (ty == DVM_FACE_FINER) {
+            cnt[f] = 4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) src[f][k] = fin + int64_t(cell.nbr(f, k)) * NV;
+            dist[f] = F(0.75 * h);
+        } else if (ty == DVM_FACE_INFLOW) {
+            src[f][0] = static_cast<const F *>(a.ghost_in);
+        }
+    }
+    for (int64_t v = threadIdx.x; v < NV; v += 256) {
+        const int o = int(v / B);
+        const F fc = own[v];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            F sig = F(0);
+            if (!wall) {
+                F nm[2];
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int f = 2 * b + side;
+                    F x = src[f][0][v];
+                    if (cnt[f] == 4) x = F(0.25) * (((x + src[f][1][v]) + src[f][2][v]) + src[f][3][v]);
+                    nm[side] = x;
+                }
+                const F sl = (fc - nm[0]) / dist[2 * b], sr = (nm[1] - fc) / dist[2 * b + 1];
+                sig = sl * sr <= F(0) ? F(0) : (fabs(sl) < fabs(sr) ? sl : sr);
+            }
+            const int sb = b == 0 ? (o >> 2) : b == 1 ? ((o >> 1) & 1) : (o & 1);
+            const F half = F(sb ? 0.5 * h : -0.5 * h);
+            face[(b * a.n_cells + c) * NV + v] = fc + half * sig;
+        }
+    }
 }
 
 // f := corrected Maxwellian of a prescribed state (init and ghost rows).
@@ -664,9 +754,27 @@ __global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelG
     X(12, 576, 5, 1)        \
     X(12, 576, 7, 1)
 
+// MUSCL step kernels: one shape per N
+#define DVM_MUSCL_CONFIGS(X) \
+    X(2, 64, 4, 0)           \
+    X(4, 64, 5, 0)           \
+    X(6, 256, 6, 0)          \
+    X(8, 256, 5, 0)          \
+    X(12, 192, 3, 1)
+
 template <typename F>
 hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t st) {
     const dim3 grid(unsigned(a.n_cells));
+    if (a.face) {
+#define X(NH, T, W, FN)                                                                        \
+        if (a.g.nh == NH) {                                                                    \
+            hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true, true>), grid, dim3(T), 0, st, a); \
+            return hipGetLastError();                                                          \
+        }
+        DVM_MUSCL_CONFIGS(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
 #define X(NH, T, W, FN)                                                                       \
     if (a.g.nh == NH && cfg.threads == T && (cfg.wpe == 0 || cfg.wpe == 10 * W + FN)) {        \
         if (cfg.nt_store) hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true>), grid, dim3(T), 0, st, a);  \
@@ -699,6 +807,20 @@ inline bool step_config_exists(int nh, int threads, int wpe) {
     DVM_STEP_CONFIGS(X)
 #undef X
     return false;
+}
+
+template <typename F>
+hipError_t face_dispatch(const StepArgs &a, hipStream_t st) {
+    const dim3 grid(unsigned(a.n_cells)), blk(256);
+    switch (a.g.nh) {
+    case 2: hipLaunchKernelGGL((k_face<F, 2>), grid, blk, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_face<F, 4>), grid, blk, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((k_face<F, 6>), grid, blk, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_face<F, 8>), grid, blk, 0, st, a); break;
+    case 12: hipLaunchKernelGGL((k_face<F, 12>), grid, blk, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename F>

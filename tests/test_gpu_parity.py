@@ -162,3 +162,40 @@ def test_engines_agree_and_switch_midway():
     assert np.abs(a["f"] - b["f"]).max() <= 1e-13 * scale
     assert np.abs(c - a["f"]).max() <= 1e-13 * scale
     assert np.abs(a["mom"] - b["mom"]).max() <= 1e-13 * np.abs(a["mom"]).max()
+
+
+# --- MUSCL-minmod (the oracle's reading of the reconstruction) -------------
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_muscl_octree_periodic_fp64(seed):
+    f = balanced(I.random_forest(10 + seed, (2, 2, 2), 3, 0.25))
+    case = Case(f, 8, 4.5, scheme=I.SCHEME_MUSCL, tau=0.05, fields="sines", field_args={"seed": 40 + seed})
+    _compare(case, 10, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_muscl_inflow_outflow_wall_fp64():
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.WALL, I.PERIODIC, I.PERIODIC)
+    f = balanced(I.random_forest(12, (2, 2, 2), 3, 0.2, bc))
+    case = Case(f, 8, 6.0, scheme=I.SCHEME_MUSCL, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, 1.3, 0.1, 0.0, 1.1),
+                t_wall=0.9, fields="sines", field_args={"seed": 19})
+    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_muscl_sphere_mach2_fp64_and_fp32():
+    """the sphere construction (inflow, outflow, staircase diffuse wall) on
+    8^3 roots with 12^3 velocities: FP64 to 1e-12, FP32 to 2e-5 on moments"""
+    f = balanced(I.sphere_refinement(base=(8, 8, 8), levels=2, radius=0.2))
+    sol = I.solid_flags(f, (0.5, 0.5, 0.5), 0.2, 2)
+    u_in = 2.0 * (5.0 / 3.0) ** 0.5
+    case = Case(f, 12, 6.0, scheme=I.SCHEME_MUSCL, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, u_in, 0.0, 0.0, 1.0),
+                solid=sol, fields="uniform", field_args={"rho": 1.0, "u": (u_in, 0.0, 0.0), "T": 1.0})
+    o, g = _compare(case, 20, D.PREC_FP32, FP32_TOL)
+    g64 = gpu_run(case, 20, D.PREC_FP64)
+    assert np.all(moment_errors(g64["mom"], o["mom"]) <= FP64_TOL)
+    assert np.abs(g64["f"] - o["f"]).max() <= FP64_TOL * np.abs(o["f"]).max()
+
+
+def test_muscl_sod_24_fp32():
+    f = I.random_root_refinement((4, 4, 4), 0.4, 3)
+    case = Case(f, 24, 6.0, scheme=I.SCHEME_MUSCL, tau_mode=I.TAU_HS, tau=0.01, fields="sod_x")
+    _compare(case, 20, D.PREC_FP32, FP32_TOL)

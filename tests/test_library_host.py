@@ -121,3 +121,25 @@ def test_solver_argument_errors_host_only():
     assert D.lib().dvm_dt(h, C.c_double(0.5), C.byref(dt)) == D.OK
     assert dt.value == 0.5 * 0.25 / (3 * 3.9375)
     D.lib().dvm_destroy_solver(h)
+
+
+def test_muscl_solver_workspace_and_engine_host_only():
+    """MUSCL adds three face-value planes to the workspace and is a
+    fused-engine scheme: asking for the deferred-collision engine is refused"""
+    import ctypes as C
+    m = D.Mesh(I.uniform_forest((1, 1, 1), 2))
+    sizes = {}
+    for scheme in (D.SCHEME_UPWIND1, D.SCHEME_MUSCL):
+        h = C.c_void_p()
+        p = D.make_params(8, 4.5, scheme=scheme)
+        assert D.lib().dvm_create_solver(m.h, C.byref(p), C.byref(h)) == D.OK
+        sz = D.Sizes()
+        assert D.lib().dvm_buffer_sizes(h, C.byref(sz)) == D.OK
+        sizes[scheme] = (sz.f_bytes, sz.ws_bytes)
+        prev = C.c_int32()
+        rc = D.lib().dvm_tune_engine(h, 1, C.byref(prev))
+        assert prev.value == 0
+        assert rc == (D.ERR_UNSUPPORTED if scheme == D.SCHEME_MUSCL else D.OK)
+        D.lib().dvm_destroy_solver(h)
+    fb = sizes[D.SCHEME_UPWIND1][0]
+    assert sizes[D.SCHEME_MUSCL][1] == sizes[D.SCHEME_UPWIND1][1] + 3 * fb
