@@ -85,6 +85,7 @@ extern "C" {
 
 typedef struct dvm_mesh dvm_mesh;
 typedef struct dvm_solver dvm_solver;
+typedef struct dvm_batch dvm_batch;
 
 typedef struct {
     int32_t base[3];          /* root cubes per axis, each >= 1 */
@@ -258,6 +259,43 @@ int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *x
  * the selected engine.
  */
 int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
+
+/*
+ * Batched steps (many independent flow instances in one graph launch).
+ *
+ * dvm_batch_create -- group n bound solvers (same storage precision, first
+ * order, fused engine) by velocity grid; inside a group the instances are
+ * ordered by decreasing cost (cells x velocities) so that the largest start
+ * first.  Each instance steps with its own dt = cfl h_min / max sum |xi|.
+ * The solvers must outlive the batch; the batch owns host objects and the
+ * recorded graphs only.
+ * dvm_batch_workspace_bytes / dvm_batch_bind -- a caller-owned device block
+ * (256-byte aligned) for the per-instance kernel arguments.
+ * dvm_batch_step -- n_steps steps of every instance: per step one launch of
+ * a recorded HIP graph holding, per velocity grid, one step kernel over the
+ * cells of all its instances, then the FP64 global sums of every instance
+ * (the values dvm_check reports).  The graphs are recorded at the first call
+ * (and after dvm_batch_tune); a solver stepped on its own in between is
+ * picked up (its buffers are re-read), DVM_ERR_WORKSPACE if a solver is not
+ * uploaded.  Results are bitwise those of dvm_step on each solver with the
+ * same kernel shape.
+ * dvm_batch_tune -- project autotuner: for every velocity-grid group, time
+ * each compiled step shape x XCD grouping {1, 8, 64} x store kind with reps
+ * launches on the batch's own data and keep the fastest.  The state the
+ * batch advances is unchanged (trial steps write only the next buffers; the
+ * moments are recomputed from the current state afterwards).  Synchronises.
+ * dvm_batch_info -- group < 0: *n_inst = number of groups; otherwise the
+ * group's velocity half-size NH (N = 2 NH), instance count, total cells and
+ * chosen shape (tuned_ms: best time per launch from the last tuning, or 0).
+ */
+int dvm_batch_create(dvm_solver *const *solvers, int32_t n, double cfl, dvm_batch **out);
+int dvm_batch_workspace_bytes(const dvm_batch *b, size_t *bytes);
+int dvm_batch_bind(dvm_batch *b, void *ws);
+int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream);
+int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream);
+int dvm_batch_info(const dvm_batch *b, int32_t group, int32_t *nh, int32_t *n_inst, int64_t *n_cells,
+                   int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store, double *tuned_ms);
+void dvm_destroy_batch(dvm_batch *b);
 
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);

@@ -68,6 +68,19 @@ bool have_kernel(int nh, int threads, int wpe);
 int list_kernels(int nh, int *threads, int *wpe, int cap);
 int default_threads(bool fp64, int nh);
 
+// Batched steps (batch.cpp): instance arguments in device memory.
+struct SumArgs {
+    const double *mom;       // [5][n]
+    const DevCell *cells;
+    int64_t n;
+    double h0;
+    double *partials;        // [kPartials][5]
+    double *out;             // [5]
+};
+hipError_t launch_step_batch(bool fp64, const StepArgs *inst, const uint32_t *wg_end, int n_inst, uint32_t total_wg,
+                             int nh, const StepConfig &cfg, hipStream_t st);
+hipError_t launch_global_sums_batch(const SumArgs *inst, int n_inst, int n_part, hipStream_t st);
+
 // Deferred-collision engine (lazy_impl.h).
 struct UnitArgsPub {
     const void *f_in;
@@ -77,7 +90,7 @@ struct UnitArgsPub {
     const DevCell *cells;
     const void *ghost_in;
     const void *wall_m1;
-    const void *null_rec;
+    const void *null_rec;    // the identity record; the sweep requires null_rec == tab + n_cells * stride
     int64_t n_cells;
     double dt;
     double h0;
@@ -98,7 +111,8 @@ struct TableArgsPub {
     int tau_mode;
     double tau_or_kn;
 };
-hipError_t launch_unit(bool fp64, const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st);
+hipError_t launch_unit_moments(bool fp64, const UnitArgsPub &a, hipStream_t st);
+hipError_t launch_sweep(bool fp64, const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st);
 hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st);
 hipError_t launch_identity(bool fp64, void *tab, int64_t n, int nh, hipStream_t st);
 hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, void *dst, int64_t n, int nh,
@@ -106,17 +120,20 @@ hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, v
 hipError_t launch_materialize(bool fp64, void *fstar, void *tab, int64_t n, int nh, hipStream_t st);
 hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, double w, hipStream_t st);
 int table_stride(int nh);
-bool have_unit_kernel(int nh, int threads, int wpe);
-int list_unit_kernels(int nh, int *threads, int *wpe, int cap);
+bool have_sweep_kernel(int nh, int threads, int wg_per_cu);
+int list_sweep_kernels(int nh, int *threads, int *wg_per_cu, int cap);
 
 // per-precision instantiations (kernels_f32.hip, kernels_f64.hip)
 #define DVM_DECLARE_PREC(SUF)                                                                            \
     hipError_t launch_step_##SUF(const StepArgs &a, const StepConfig &cfg, hipStream_t st);              \
+    hipError_t launch_step_batch_##SUF(const StepArgs *inst, const uint32_t *wg_end, int n_inst,         \
+                                       uint32_t total_wg, int nh, const StepConfig &cfg, hipStream_t st); \
     hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
     hipError_t launch_face_##SUF(const StepArgs &a, hipStream_t st);                                     \
     hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
     hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);              \
-    hipError_t launch_unit_##SUF(const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st); \
+    hipError_t launch_unit_moments_##SUF(const UnitArgsPub &a, hipStream_t st);                          \
+    hipError_t launch_sweep_##SUF(const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st); \
     hipError_t launch_tables_##SUF(const TableArgsPub &a, hipStream_t st);                               \
     hipError_t launch_identity_##SUF(void *tab, int64_t n, int nh, hipStream_t st);                      \
     hipError_t launch_canon_relaxed_##SUF(const void *fstar, const void *tab, void *dst, int64_t n, int nh, \

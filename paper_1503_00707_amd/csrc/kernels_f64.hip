@@ -1,10 +1,14 @@
 // kernels_f64.hip -- step, init, moment and wall kernels for double storage.
-#include "lazy_impl.h"
+#include "sweep_impl.h"
 
 namespace dvm {
 
 hipError_t launch_step_f64(const StepArgs &a, const StepConfig &cfg, hipStream_t st) {
     return impl::step_dispatch<double>(a, cfg, st);
+}
+hipError_t launch_step_batch_f64(const StepArgs *inst, const uint32_t *wg_end, int n_inst, uint32_t total_wg,
+                                 int nh, const StepConfig &cfg, hipStream_t st) {
+    return impl::step_batch_dispatch<double>(inst, wg_end, n_inst, total_wg, nh, cfg, st);
 }
 hipError_t launch_init_f64(const InitArgs &a, hipStream_t st) { return impl::init_dispatch<double>(a, st); }
 hipError_t launch_face_f64(const StepArgs &a, hipStream_t st) { return impl::face_dispatch<double>(a, st); }
@@ -18,10 +22,15 @@ hipError_t launch_wall_den_f64(const void *m1, double *den, const VelGrid &g, hi
 static_assert(sizeof(UnitArgsPub) == sizeof(impl::UnitArgs), "argument layout");
 static_assert(sizeof(TableArgsPub) == sizeof(impl::TableArgs), "argument layout");
 
-hipError_t launch_unit_f64(const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st) {
+hipError_t launch_unit_moments_f64(const UnitArgsPub &a, hipStream_t st) {
     impl::UnitArgs u;
     __builtin_memcpy(&u, &a, sizeof u);
-    return impl::unit_dispatch<double>(u, threads, wpe, transport, nt, st);
+    return impl::unit_dispatch<double>(u, st);
+}
+hipError_t launch_sweep_f64(const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st) {
+    impl::UnitArgs u;
+    __builtin_memcpy(&u, &a, sizeof u);
+    return impl::sweep_dispatch<double>(u, wg_per_cu, n_cu, nt, st);
 }
 hipError_t launch_tables_f64(const TableArgsPub &a, hipStream_t st) {
     impl::TableArgs t;

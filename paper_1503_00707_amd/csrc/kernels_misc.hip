@@ -2,7 +2,7 @@
 // precision dispatch of the launch interface.
 #include <hip/hip_runtime.h>
 
-#include "lazy_impl.h"
+#include "sweep_impl.h"
 
 namespace dvm {
 namespace {
@@ -32,6 +32,38 @@ __global__ __launch_bounds__(256) void k_sums_stage2(const double *partials, int
     impl::block_sum<256, 5>(v, red);
     if (threadIdx.x == 0)
         for (int k = 0; k < 5; ++k) out[k] = v[k];
+}
+
+// The same two-level sums for many instances in two launches: workgroup
+// (instance i, block p) of stage 1 covers the same cell range as block p of
+// k_sums_stage1 for that instance, so both paths agree bitwise.
+__global__ __launch_bounds__(256) void k_sums_batch1(const SumArgs *inst, int n_part) {
+    __shared__ double red[4 * 5];
+    const int i = blockIdx.x / n_part, blk = blockIdx.x % n_part;
+    const SumArgs a = inst[i];
+    const int64_t n = a.n;
+    const int64_t chunk = (n + n_part - 1) / n_part;
+    const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t c = lo + threadIdx.x; c < hi; c += 256) {
+        const double h = a.h0 / double(1 << a.cells[c].level);
+        const double V = h * h * h;
+        for (int k = 0; k < 5; ++k) v[k] += V * a.mom[k * n + c];
+    }
+    impl::block_sum<256, 5>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) a.partials[blk * 5 + k] = v[k];
+}
+
+__global__ __launch_bounds__(256) void k_sums_batch2(const SumArgs *inst, int n_part) {
+    __shared__ double red[4 * 5];
+    const SumArgs a = inst[blockIdx.x];
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < n_part; b += 256)
+        for (int k = 0; k < 5; ++k) v[k] += a.partials[b * 5 + k];
+    impl::block_sum<256, 5>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k) a.out[k] = v[k];
 }
 
 // canonical index (kx*N + ky)*N + kz  <->  internal octant-major index
@@ -71,6 +103,20 @@ hipError_t launch_step(bool fp64, const StepArgs &a, const StepConfig &cfg, hipS
     return fp64 ? launch_step_f64(a, cfg, st) : launch_step_f32(a, cfg, st);
 }
 
+hipError_t launch_step_batch(bool fp64, const StepArgs *inst, const uint32_t *wg_end, int n_inst, uint32_t total_wg,
+                             int nh, const StepConfig &cfg, hipStream_t st) {
+    return fp64 ? launch_step_batch_f64(inst, wg_end, n_inst, total_wg, nh, cfg, st)
+                : launch_step_batch_f32(inst, wg_end, n_inst, total_wg, nh, cfg, st);
+}
+
+hipError_t launch_global_sums_batch(const SumArgs *inst, int n_inst, int n_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_sums_batch1, dim3(unsigned(n_inst * n_part)), dim3(256), 0, st, inst, n_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sums_batch2, dim3(unsigned(n_inst)), dim3(256), 0, st, inst, n_part);
+    return hipGetLastError();
+}
+
 hipError_t launch_face(bool fp64, const StepArgs &a, hipStream_t st) {
     return fp64 ? launch_face_f64(a, st) : launch_face_f32(a, st);
 }
@@ -87,8 +133,11 @@ hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid
     return fp64 ? launch_wall_den_f64(m1, den, g, st) : launch_wall_den_f32(m1, den, g, st);
 }
 
-hipError_t launch_unit(bool fp64, const UnitArgsPub &a, int threads, int wpe, bool transport, bool nt, hipStream_t st) {
-    return fp64 ? launch_unit_f64(a, threads, wpe, transport, nt, st) : launch_unit_f32(a, threads, wpe, transport, nt, st);
+hipError_t launch_unit_moments(bool fp64, const UnitArgsPub &a, hipStream_t st) {
+    return fp64 ? launch_unit_moments_f64(a, st) : launch_unit_moments_f32(a, st);
+}
+hipError_t launch_sweep(bool fp64, const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st) {
+    return fp64 ? launch_sweep_f64(a, wg_per_cu, n_cu, nt, st) : launch_sweep_f32(a, wg_per_cu, n_cu, nt, st);
 }
 hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st) {
     return fp64 ? launch_tables_f64(a, st) : launch_tables_f32(a, st);
@@ -108,8 +157,8 @@ hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, d
     return hipGetLastError();
 }
 int table_stride(int nh) { return impl::tab_stride(nh); }
-bool have_unit_kernel(int nh, int threads, int wpe) { return impl::unit_config_exists(nh, threads, wpe); }
-int list_unit_kernels(int nh, int *threads, int *wpe, int cap) { return impl::unit_config_list(nh, threads, wpe, cap); }
+bool have_sweep_kernel(int nh, int threads, int k) { return impl::sweep_config_exists(nh, threads, k); }
+int list_sweep_kernels(int nh, int *threads, int *k, int cap) { return impl::sweep_config_list(nh, threads, k, cap); }
 
 hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
                               int n_part, double *out, hipStream_t st) {

@@ -43,17 +43,15 @@ struct TabLayout {
     static constexpr int kStride = 6 * N + 8;
 };
 
+
 // The cell record read with runtime face indices (scalar loads from memory).
 struct CellPtr {
-    const uint32_t *p;
-    __device__ __forceinline__ CellPtr(const DevCell *cells, int64_t c) : p(reinterpret_cast<const uint32_t *>(cells + c)) {}
-    __device__ __forceinline__ int type(int f) const {
-        return (__builtin_amdgcn_readfirstlane(p[24 + (f >> 2)]) >> (8 * (f & 3))) & 0xff;
-    }
-    __device__ __forceinline__ int level() const { return (__builtin_amdgcn_readfirstlane(p[25]) >> 16) & 0xff; }
-    __device__ __forceinline__ int32_t nbr(int f, int k) const {
-        return int32_t(__builtin_amdgcn_readfirstlane(p[4 * f + k]));
-    }
+    cuint32_t *p;
+    __device__ __forceinline__ CellPtr(const DevCell *cells, int64_t c)
+        : p(as_const_space(reinterpret_cast<const uint32_t *>(cells + c))) {}
+    __device__ __forceinline__ int type(int f) const { return (p[24 + (f >> 2)] >> (8 * (f & 3))) & 0xff; }
+    __device__ __forceinline__ int level() const { return (p[25] >> 16) & 0xff; }
+    __device__ __forceinline__ int32_t nbr(int f, int k) const { return int32_t(p[4 * f + k]); }
 };
 
 struct UnitArgs {
@@ -76,14 +74,15 @@ struct UnitArgs {
 // x factors are workgroup-uniform (scalar loads), y/z factors per lane.
 template <typename F, int NH>
 struct RecView {
-    const F *rec;
+    cF<F> *rec;  // x factors and e: uniform, scalar loads
     F gyz, pyz, e;
     int sx;
-    __device__ __forceinline__ RecView(const F *r, int ky, int kz, int sx_) : rec(r), sx(sx_) {
+    __device__ __forceinline__ RecView(const F *r, int ky, int kz, int sx_)
+        : rec(as_const_space(r)), sx(sx_) {
         constexpr int N = 2 * NH;
         gyz = r[2 * (N + ky)] * r[2 * (2 * N + kz)];
         pyz = r[2 * (N + ky) + 1] + r[2 * (2 * N + kz) + 1];
-        e = r[6 * N];
+        e = rec[6 * N];
     }
     __device__ __forceinline__ F apply(int ax, F fstar) const {
         const int kx = sx ? NH + ax : NH - 1 - ax;
@@ -408,57 +407,27 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *partials, do
     for (int k = 0; k < 5; ++k) out[k * n + c] = w * m[k];
 }
 
-// ---------------------------------------------------------------------------
-// unit shapes: (NH, K, TL, WPE); TA = K NH^2 active threads of TL launched
-// ---------------------------------------------------------------------------
+// Partial moments of the relaxed state (no transport): one shape per N.
 #define DVM_UNIT_CONFIGS(X) \
     X(2, 64, 8)             \
     X(4, 64, 8)             \
     X(6, 64, 8)             \
     X(8, 64, 8)             \
-    X(12, 192, 4)           \
-    X(12, 192, 5)           \
-    X(12, 192, 6)           \
-    X(12, 192, 8)
+    X(12, 192, 5)
 
 template <typename F>
-hipError_t unit_dispatch(const UnitArgs &a, int tl, int wpe, bool transport, bool nt, hipStream_t st) {
+hipError_t unit_dispatch(const UnitArgs &a, hipStream_t st) {
     const int64_t units = 8 * a.n_cells;
     const unsigned gx = unsigned(units < 8 * 16384 ? units : 8 * 16384);
     const dim3 grid(gx, unsigned((units + gx - 1) / gx));
-#define X(NH, TL, W)                                                                                    \
-    if (a.g.nh == NH && (tl == 0 || tl == TL) && (wpe == 0 || wpe == W)) {                              \
-        if (!transport) hipLaunchKernelGGL((k_unit<F, NH, TL, W, false, false>), grid, dim3(TL), 0, st, a); \
-        else if (nt) hipLaunchKernelGGL((k_unit<F, NH, TL, W, true, true>), grid, dim3(TL), 0, st, a);  \
-        else hipLaunchKernelGGL((k_unit<F, NH, TL, W, true, false>), grid, dim3(TL), 0, st, a);         \
-        return hipGetLastError();                                                                       \
+#define X(NH, TL, W)                                                                              \
+    if (a.g.nh == NH) {                                                                           \
+        hipLaunchKernelGGL((k_unit<F, NH, TL, W, false, false>), grid, dim3(TL), 0, st, a);       \
+        return hipGetLastError();                                                                 \
     }
     DVM_UNIT_CONFIGS(X)
 #undef X
     return hipErrorInvalidValue;
-}
-
-inline int unit_config_list(int nh, int *threads, int *wpe, int cap) {
-    int n = 0;
-#define X(NH, TL, W)        \
-    if (nh == NH) {         \
-        if (n < cap) {      \
-            threads[n] = TL; \
-            wpe[n] = W;     \
-        }                   \
-        ++n;                \
-    }
-    DVM_UNIT_CONFIGS(X)
-#undef X
-    return n;
-}
-
-inline bool unit_config_exists(int nh, int threads, int wpe) {
-#define X(NH, TL, W) \
-    if (nh == NH && threads == TL && (wpe == 0 || wpe == W)) return true;
-    DVM_UNIT_CONFIGS(X)
-#undef X
-    return false;
 }
 
 template <typename F>

@@ -7,65 +7,9 @@
 #include <cstring>
 #include <new>
 
-#include "internal.h"
-#include "kernels.h"
+#include "solver_impl.h"
 
 using namespace dvm;
-
-namespace {
-
-constexpr int kPartials = 1024;  // blocks of the first global-sum stage
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-int hip_fail(hipError_t e, const char *what) {
-    return fail(DVM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-}  // namespace
-
-struct dvm_solver {
-    const dvm_mesh *m = nullptr;
-    dvm_params p{};
-    bool fp64 = false;
-    int nh = 0;
-    int64_t nv = 0;
-    int64_t n = 0;
-    VelGrid g{};
-    StepConfig cfg{};
-    size_t f_bytes = 0, mom_bytes = 0, tab_bytes = 0, ws_bytes = 0;
-    // workspace sections (byte offsets)
-    size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
-    size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
-    bool muscl = false;
-    void *f[2] = {nullptr, nullptr};
-    int cur = 0;
-    double *mom = nullptr;
-    DevCell *tables = nullptr;
-    char *ws = nullptr;
-    bool uploaded = false;
-    int64_t steps = 0;
-    bool has_inflow = false, has_wall = false;
-    // deferred-collision engine
-    int engine = 0;              // 0: fused (stores f), 1: deferred collision (stores f* + records)
-    int unit_threads = 0, unit_wpe = 0, unit_nt = 1;
-    size_t off_tab = 0, off_lpart = 0, off_null = 0;
-    bool lazy_valid = false;     // records describe f[cur] read as f*
-    bool relax_pending = false;  // some record is not the identity
-
-    void *tab() const { return ws + off_tab; }
-    void *null_rec() const { return ws + off_null; }
-    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
-    void *gin() const { return ws + off_gin; }
-    void *face() const { return muscl ? ws + off_face : nullptr; }
-    void *m1() const { return ws + off_m1; }
-    double *den() const { return reinterpret_cast<double *>(ws + off_den); }
-    int *flag() const { return reinterpret_cast<int *>(ws + off_flag); }
-    double *partials() const { return reinterpret_cast<double *>(ws + off_part); }
-    double *sums() const { return reinterpret_cast<double *>(ws + off_sums); }
-};
-
-static hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
 
 static UnitArgsPub unit_args(const dvm_solver *s, const void *fin, void *fout, double dt) {
     UnitArgsPub u{};
@@ -110,7 +54,7 @@ static hipError_t ensure_lazy(dvm_solver *s, hipStream_t st) {
     hipError_t e = launch_identity(s->fp64, s->tab(), s->n, s->nh, st);
     if (e != hipSuccess) return e;
     UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
-    e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, false, false, st);
+    e = launch_unit_moments(s->fp64, u, st);
     if (e != hipSuccess) return e;
     TableArgsPub t = table_args(s, 0, 0.0, s->mom);
     e = launch_tables(s->fp64, t, st);
@@ -121,7 +65,28 @@ static hipError_t ensure_lazy(dvm_solver *s, hipStream_t st) {
 }
 
 // Apply a pending relaxation in place so that the buffer holds f itself.
-static hipError_t ensure_plain(dvm_solver *s, hipStream_t st) {
+StepArgs dvm::solver_step_args(const dvm_solver *s, double dt) {
+    StepArgs a{};
+    a.mom = s->mom;
+    a.cells = s->tables;
+    a.ghost_in = s->gin();
+    a.wall_m1 = s->m1();
+    a.wall_den = s->den();
+    a.flag = s->flag();
+    a.n_cells = s->n;
+    a.dt = dt;
+    a.h0 = s->m->h0;
+    a.g = s->g;
+    a.collision = s->p.collision;
+    a.tau_mode = s->p.tau_mode;
+    a.tau_or_kn = s->p.tau_or_kn;
+    a.xcd_log2 = 0;
+    while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
+    a.face = s->face();
+    return a;
+}
+
+hipError_t dvm::solver_make_plain(dvm_solver *s, hipStream_t st) {
     if (!s->relax_pending) return hipSuccess;
     hipError_t e = launch_materialize(s->fp64, s->f[s->cur], s->tab(), s->n, s->nh, st);
     if (e != hipSuccess) return e;
@@ -129,7 +94,7 @@ static hipError_t ensure_plain(dvm_solver *s, hipStream_t st) {
     return hipSuccess;
 }
 
-static double max_speed_sum(const dvm_solver *s) {
+double dvm::solver_max_speed_sum(const dvm_solver *s) {
     double r = 0.0;
     for (int b = 0; b < 3; ++b) r += (s->nh - 0.5) * s->g.dv[b];
     return r;
@@ -191,21 +156,15 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->off_flag = o; o += 256;
     s->off_part = o; o += align256(size_t(kPartials) * 5 * 8);
     s->off_sums = o; o += 256;
-    s->off_tab = o;  o += align256(size_t(s->n) * size_t(table_stride(nh)) * fs);
+    // n records and the identity record after them (one table for the sweep)
+    s->off_tab = o;  o += align256(size_t(s->n + 1) * size_t(table_stride(nh)) * fs);
+    s->off_null = s->off_tab + size_t(s->n) * size_t(table_stride(nh)) * fs;
     s->off_lpart = o; o += align256(size_t(8) * size_t(s->n) * 5 * 8);
-    s->off_null = o; o += align256(size_t(table_stride(nh)) * fs);
     s->muscl = p->scheme == DVM_SCHEME_MUSCL;
     s->off_face = o;
     if (s->muscl) o += 3 * s->f_bytes;
     s->ws_bytes = o;
-    {
-        int t[16], w[16];
-        if (list_unit_kernels(nh, t, w, 16) > 0) {
-            s->unit_threads = t[0];
-            s->unit_wpe = w[0];
-        }
-        if (nh == 12) s->unit_wpe = 5;
-    }
+    if (nh == 12) s->sweep_k = 3;
     *out = s;
     return DVM_OK;
 }
@@ -274,6 +233,12 @@ int dvm_upload(dvm_solver *s, void *stream) {
     }
     e = launch_identity(s->fp64, s->null_rec(), 1, s->nh, st);
     if (e != hipSuccess) return hip_fail(e, "identity record");
+    {
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "device attributes");
+    }
     // the host table must stay valid until the copy has been consumed
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -307,7 +272,7 @@ int dvm_dt(const dvm_solver *s, double cfl, double *dt) {
     clear_error();
     if (!s || !dt) return fail(DVM_ERR_ARG, "null argument");
     if (!(cfl > 0)) return fail(DVM_ERR_ARG, "cfl must be > 0");
-    *dt = cfl * s->m->h_min / max_speed_sum(s);
+    *dt = cfl * s->m->h_min / solver_max_speed_sum(s);
     return DVM_OK;
 }
 
@@ -320,31 +285,15 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
         int rc = dvm_dt(s, cfl, &dt);
         if (rc) return rc;
     }
-    StepArgs a{};
-    a.mom = s->mom;
-    a.cells = s->tables;
-    a.ghost_in = s->gin();
-    a.wall_m1 = s->m1();
-    a.wall_den = s->den();
-    a.flag = s->flag();
-    a.n_cells = s->n;
-    a.dt = dt;
-    a.h0 = s->m->h0;
-    a.g = s->g;
-    a.collision = s->p.collision;
-    a.tau_mode = s->p.tau_mode;
-    a.tau_or_kn = s->p.tau_or_kn;
-    a.xcd_log2 = 0;
-    while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
-    a.face = s->face();
+    StepArgs a = solver_step_args(s, dt);
     hipStream_t st = S(stream);
-    hipError_t e = s->engine == 1 ? ensure_lazy(s, st) : ensure_plain(s, st);
+    hipError_t e = s->engine == 1 ? ensure_lazy(s, st) : solver_make_plain(s, st);
     if (e != hipSuccess) return hip_fail(e, "state conversion");
     for (int it = 0; it < n_steps; ++it) {
         if (s->engine == 1) {
             UnitArgsPub u = unit_args(s, s->f[s->cur], s->f[s->cur ^ 1], dt);
-            e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, true, s->unit_nt != 0, st);
-            if (e != hipSuccess) return hip_fail(e, "transport units");
+            e = launch_sweep(s->fp64, u, s->sweep_k, s->n_cu, s->unit_nt != 0, st);
+            if (e != hipSuccess) return hip_fail(e, "transport sweep");
             TableArgsPub t = table_args(s, 1, dt, s->mom);
             e = launch_tables(s->fp64, t, st);
             if (e != hipSuccess) return hip_fail(e, "collision records");
@@ -393,7 +342,7 @@ int dvm_moments(dvm_solver *s, double *out, void *stream) {
     hipError_t e;
     if (s->relax_pending) {
         UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
-        e = launch_unit(s->fp64, u, s->unit_threads, s->unit_wpe, false, false, S(stream));
+        e = launch_unit_moments(s->fp64, u, S(stream));
         if (e == hipSuccess) e = launch_sum_partials(s->lpart(), out, s->n, s->g.w, S(stream));
     } else {
         e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
@@ -452,7 +401,7 @@ int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t
     clear_error();
     if (!s || !n || (cap > 0 && (!threads || !wpe))) return fail(DVM_ERR_ARG, "null argument");
     int t[64], w[64];
-    const int total = s->engine == 1 ? list_unit_kernels(s->nh, t, w, 64) : list_kernels(s->nh, t, w, 64);
+    const int total = s->engine == 1 ? list_sweep_kernels(s->nh, t, w, 64) : list_kernels(s->nh, t, w, 64);
     for (int k = 0; k < total && k < cap && k < 64; ++k) {
         threads[k] = t[k];
         wpe[k] = w[k];
@@ -467,10 +416,10 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
     if (xcd_group < 1 || xcd_group > 4096 || (xcd_group & (xcd_group - 1)))
         return fail(DVM_ERR_ARG, "xcd_group must be a power of two in [1, 4096]");
     if (s->engine == 1) {
-        if (!have_unit_kernel(s->nh, threads, wpe))
-            return fail(DVM_ERR_UNSUPPORTED, "no unit kernel with %d threads, wpe %d for N = %d", threads, wpe, 2 * s->nh);
-        s->unit_threads = threads;
-        s->unit_wpe = wpe;
+        if (!have_sweep_kernel(s->nh, threads, wpe))
+            return fail(DVM_ERR_UNSUPPORTED, "no sweep kernel with %d threads, %d workgroups per CU for N = %d",
+                        threads, wpe, 2 * s->nh);
+        s->sweep_k = wpe;
         s->unit_nt = nt_store != 0;
         s->cfg.xcd_group = xcd_group;
         return DVM_OK;
@@ -487,8 +436,12 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
 int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store) {
     clear_error();
     if (!s || !threads || !wpe || !xcd_group || !nt_store) return fail(DVM_ERR_ARG, "null argument");
-    *threads = s->engine == 1 ? s->unit_threads : s->cfg.threads;
-    *wpe = s->engine == 1 ? s->unit_wpe : s->cfg.wpe;
+    int t1[64], k1[64];
+    const int nk = list_sweep_kernels(s->nh, t1, k1, 64);
+    int k = s->sweep_k;
+    if (k == 0 && nk > 0) k = k1[0];
+    *threads = s->engine == 1 ? (nk > 0 ? t1[0] : 0) : s->cfg.threads;
+    *wpe = s->engine == 1 ? k : s->cfg.wpe;
     *xcd_group = s->cfg.xcd_group;
     *nt_store = s->engine == 1 ? s->unit_nt : s->cfg.nt_store;
     return DVM_OK;
@@ -501,6 +454,8 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous) {
     if (engine < 0) return DVM_OK;  // query only
     if (engine != 0 && engine != 1) return fail(DVM_ERR_ARG, "engine must be 0 (fused) or 1 (deferred collision)");
     if (engine == 1 && s->muscl) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine is first order only");
+    if (engine == 1 && size_t(s->n + 1) * size_t(table_stride(s->nh)) * (s->fp64 ? 8 : 4) >= (size_t(1) << 32))
+        return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine addresses its records with 32-bit offsets");
     s->engine = engine;
     return DVM_OK;
 }

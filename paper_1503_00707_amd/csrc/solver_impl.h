@@ -1,0 +1,74 @@
+// solver_impl.h -- the solver object shared by the host sources (solver.cpp,
+// batch.cpp).  Holds no device memory of its own: every buffer is bound by
+// the caller (dvm_bind).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace dvm {
+
+constexpr int kPartials = 1024;  // blocks of the first global-sum stage
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline int hip_fail(hipError_t e, const char *what) {
+    return fail(DVM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
+
+}  // namespace dvm
+
+struct dvm_solver {
+    const dvm_mesh *m = nullptr;
+    dvm_params p{};
+    bool fp64 = false;
+    int nh = 0;
+    int64_t nv = 0;
+    int64_t n = 0;
+    dvm::VelGrid g{};
+    dvm::StepConfig cfg{};
+    size_t f_bytes = 0, mom_bytes = 0, tab_bytes = 0, ws_bytes = 0;
+    // workspace sections (byte offsets)
+    size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
+    size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
+    bool muscl = false;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *mom = nullptr;
+    dvm::DevCell *tables = nullptr;
+    char *ws = nullptr;
+    bool uploaded = false;
+    int64_t steps = 0;
+    bool has_inflow = false, has_wall = false;
+    // deferred-collision engine
+    int engine = 0;              // 0: fused (stores f), 1: deferred collision (stores f* + records)
+    int sweep_k = 0, unit_nt = 1;  // sweep workgroups per CU (0: first compiled), NT stores
+    int n_cu = 0;                  // compute units of the bound device
+    size_t off_tab = 0, off_lpart = 0, off_null = 0;
+    bool lazy_valid = false;     // records describe f[cur] read as f*
+    bool relax_pending = false;  // some record is not the identity
+
+    void *tab() const { return ws + off_tab; }
+    void *null_rec() const { return ws + off_null; }  // record n of the table section
+    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
+    void *gin() const { return ws + off_gin; }
+    void *face() const { return muscl ? ws + off_face : nullptr; }
+    void *m1() const { return ws + off_m1; }
+    double *den() const { return reinterpret_cast<double *>(ws + off_den); }
+    int *flag() const { return reinterpret_cast<int *>(ws + off_flag); }
+    double *partials() const { return reinterpret_cast<double *>(ws + off_part); }
+    double *sums() const { return reinterpret_cast<double *>(ws + off_sums); }
+};
+
+
+namespace dvm {
+// The state buffer holds f itself (applies a pending deferred relaxation).
+hipError_t solver_make_plain(dvm_solver *s, hipStream_t st);
+// Kernel arguments of one fused step of size dt (f_in / f_out left NULL).
+StepArgs solver_step_args(const dvm_solver *s, double dt);
+double solver_max_speed_sum(const dvm_solver *s);
+}  // namespace dvm

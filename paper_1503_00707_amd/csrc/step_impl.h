@@ -40,6 +40,17 @@ namespace impl {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
+// Read-only data with a workgroup-uniform address, read through the constant
+// address space so that the loads are scalar (they do not count against the
+// vector-memory counter of the data loads in flight).
+typedef __attribute__((address_space(4))) const uint32_t cuint32_t;
+template <typename F>
+using cF = __attribute__((address_space(4))) const F;
+template <typename T>
+__device__ __forceinline__ cF<T> *as_const_space(const T *p) {
+    return (cF<T> *)p;  // generic -> constant address space (a C cast: no C++ cast crosses spaces)
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -233,7 +244,8 @@ __device__ inline double gram_entry(int i, int j, const double *X, const double 
 // definite, so no pivoting).  tab[0] carries C * mfac, so that the table
 // product is mfac * Mt.
 template <typename F, int NH, int T>
-__device__ void maxwell_solve(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, const VelGrid &g) {
+__device__ __forceinline__ void maxwell_solve(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt,
+                                              const VelGrid &g) {
     constexpr int N = 2 * NH;
     constexpr int NW = (T + 63) / 64;
     static_assert(N <= 64, "one wave per axis");
@@ -306,8 +318,8 @@ __device__ void maxwell_fill(MaxwellSmem<F, NH> &sm, double mfac) {
 }
 
 template <typename F, int NH, int T>
-__device__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt, double mfac,
-                               const VelGrid &g) {
+__device__ __forceinline__ void maxwell_tables(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt,
+                                               double mfac, const VelGrid &g) {
     maxwell_solve<F, NH, T>(sm, rho, u, Tt, g);
     maxwell_fill<F, NH, T>(sm, mfac);
 }
@@ -471,18 +483,16 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
     }
 }
 
-// One fused step for one cell per workgroup.
-template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
+// One fused step of cell c by the calling workgroup.
+template <typename F, int NH, int T, int FENCE, bool NT, bool MU>
+__device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem<F, NH, T> &sm) {
     constexpr int B = NH * NH * NH;
     constexpr int64_t NV = 8 * B;
     using L = Lane<NH, T>;
     constexpr int S = L::S;
-    __shared__ StepSmem<F, NH, T> sm;
 
     const int tid = threadIdx.x;
     const L ln;
-    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const CellView cell(a.cells, c);
     const F *fin = static_cast<const F *>(a.f_in);
     constexpr uint32_t kRow = uint32_t(NV * sizeof(F));
@@ -499,6 +509,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
 
     // diffuse walls: density of the re-emitted Maxwellian (zero net mass flux)
     if (cell.flags() & 1) {
+#pragma unroll
         for (int f = 0; f < 6; ++f) {
             if (cell.type(f) != DVM_FACE_WALL) continue;
             const int axis = f >> 1, side = f & 1;
@@ -584,6 +595,41 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     }
     maxwell_tables<F, NH, T>(sm.mx, rho, u, Tt, mfac, a.g);
     relax_store<F, NH, T, NT>(sm.mx, fo, F(e), out);
+}
+
+// One fused step, one cell per workgroup.
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
+    __shared__ StepSmem<F, NH, T> sm;
+    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
+    step_cell<F, NH, T, FENCE, NT, MU>(a, c, sm);
+}
+
+// Batched step: the cells of many independent instances with the same
+// velocity grid size in one launch.  Workgroups [wg_end[i-1], wg_end[i]) serve
+// instance i (instances listed by decreasing cost, so that the largest start
+// first); each reads its instance's arguments with scalar loads.
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step_batch(
+    const StepArgs *inst, const uint32_t *wg_end, int n_inst, int xcd_log2) {
+    __shared__ StepSmem<F, NH, T> sm;
+    const uint32_t b = remap_cell(blockIdx.x, gridDim.x, xcd_log2);
+    cuint32_t *we = as_const_space(wg_end);
+    int lo = 0, hi = n_inst - 1;  // first i with wg_end[i] > b
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (we[mid] > b) hi = mid;
+        else lo = mid + 1;
+    }
+    const uint32_t start = lo == 0 ? 0u : we[lo - 1];
+    // the instance's arguments in LDS (a private copy would live in scratch
+    // memory: the step indexes some of its fields with runtime values)
+    __shared__ StepArgs a;
+    static_assert(sizeof(StepArgs) % 4 == 0 && sizeof(StepArgs) / 4 <= T, "argument words");
+    if (threadIdx.x < sizeof(StepArgs) / 4)
+        reinterpret_cast<uint32_t *>(&a)[threadIdx.x] = reinterpret_cast<const uint32_t *>(inst + lo)[threadIdx.x];
+    __syncthreads();
+    step_cell<F, NH, T, FENCE, NT, false>(a, int64_t(b - start), sm);
 }
 
 // MUSCL-minmod face values of the state a.f_in, three planes [3][n][NV] at
@@ -780,6 +826,25 @@ hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t s
         if (cfg.nt_store) hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true>), grid, dim3(T), 0, st, a);  \
         else hipLaunchKernelGGL((k_step<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, a);    \
         return hipGetLastError();                                                             \
+    }
+    DVM_STEP_CONFIGS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename F>
+hipError_t step_batch_dispatch(const StepArgs *inst, const uint32_t *wg_end, int n_inst, uint32_t total_wg, int nh,
+                               const StepConfig &cfg, hipStream_t st) {
+    int lg = 0;
+    while ((1 << (lg + 1)) <= cfg.xcd_group) ++lg;
+    const dim3 grid(total_wg);
+#define X(NH, T, W, FN)                                                                                     \
+    if (nh == NH && cfg.threads == T && (cfg.wpe == 0 || cfg.wpe == 10 * W + FN)) {                         \
+        if (cfg.nt_store)                                                                                   \
+            hipLaunchKernelGGL((k_step_batch<F, NH, T, W, FN, true>), grid, dim3(T), 0, st, inst, wg_end, n_inst, lg); \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_step_batch<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, inst, wg_end, n_inst, lg); \
+        return hipGetLastError();                                                                           \
     }
     DVM_STEP_CONFIGS(X)
 #undef X

@@ -27,6 +27,8 @@ EXPORTED = [
     "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
     "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
     "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine",
+    "dvm_batch_create", "dvm_batch_workspace_bytes", "dvm_batch_bind", "dvm_batch_step", "dvm_batch_tune",
+    "dvm_batch_info", "dvm_destroy_batch",
 ]
 
 
@@ -97,6 +99,14 @@ def lib():
         L.dvm_tune_engine.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_destroy_solver.argtypes = [P]
         L.dvm_destroy_solver.restype = None
+        L.dvm_batch_create.argtypes = [P, C.c_int32, C.c_double, C.POINTER(P)]
+        L.dvm_batch_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.dvm_batch_bind.argtypes = [P, P]
+        L.dvm_batch_step.argtypes = [P, C.c_int32, P]
+        L.dvm_batch_tune.argtypes = [P, C.c_int32, P]
+        L.dvm_batch_info.argtypes = [P, C.c_int32, P, P, P, P, P, P, P, P]
+        L.dvm_destroy_batch.argtypes = [P]
+        L.dvm_destroy_batch.restype = None
         _LIB = L
     return _LIB
 
@@ -160,9 +170,12 @@ class Mesh:
         return dict(input=inp, key=key, type=ty, nbr=nb)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dvm_destroy_mesh(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().dvm_destroy_mesh(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown
+            pass
 
 
 def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=COLL_EXP, tau_mode=TAU_CONST,
@@ -282,6 +295,58 @@ class Solver:
         return tuple(int(x) for x in v)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().dvm_destroy_solver(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().dvm_destroy_solver(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown
+            pass
+
+
+class Batch:
+    """Many solvers advanced by one graph launch per step (dvm_batch_*)."""
+
+    def __init__(self, solvers, cfl=0.5):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)  # keep them alive
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = C.c_void_p()
+        _check(lib().dvm_batch_create(arr, len(self.solvers), float(cfl), C.byref(h)), "dvm_batch_create")
+        self.h = h
+        nb = C.c_size_t(0)
+        _check(lib().dvm_batch_workspace_bytes(h, C.byref(nb)), "dvm_batch_workspace_bytes")
+        self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device="cuda")
+        _check(lib().dvm_batch_bind(h, self.ws.data_ptr()), "dvm_batch_bind")
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def step(self, n=1):
+        _check(lib().dvm_batch_step(self.h, int(n), self.stream()), "dvm_batch_step")
+
+    def tune(self, reps=3):
+        _check(lib().dvm_batch_tune(self.h, int(reps), self.stream()), "dvm_batch_tune")
+
+    def groups(self):
+        n = C.c_int32(0)
+        _check(lib().dvm_batch_info(self.h, -1, None, C.byref(n), None, None, None, None, None, None),
+               "dvm_batch_info")
+        out = []
+        for g in range(n.value):
+            v = [C.c_int32(0) for _ in range(7)]
+            cells = C.c_int64(0)
+            ms = C.c_double(0)
+            _check(lib().dvm_batch_info(self.h, g, C.byref(v[0]), C.byref(v[1]), C.byref(cells), C.byref(v[2]),
+                                        C.byref(v[3]), C.byref(v[4]), C.byref(v[5]), C.byref(ms)), "dvm_batch_info")
+            out.append(dict(nh=v[0].value, instances=v[1].value, cells=cells.value, threads=v[2].value,
+                            wpe=v[3].value, xcd_group=v[4].value, nt_store=v[5].value, tuned_ms=ms.value))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().dvm_destroy_batch(self.h)
+                self.h = None
+        except Exception:
+            pass

@@ -188,6 +188,33 @@ def fields(recipe: str, x: np.ndarray, **kw) -> np.ndarray:
 # workloads shaped like the paper's
 # ----------------------------------------------------------------------------
 
+def batch_workloads(seed: int = 4, count: int = 64, cells_lo: float = 4e3, cells_hi: float = 2e5,
+                    grids=(12, 16, 24), vmax: float = 6.0, kn: float = 0.05) -> list:
+    """Independent periodic instances of uneven size for batched stepping:
+    target cell counts log-uniform in [cells_lo, cells_hi]; half uniform root
+    lattices, half with a seeded fraction U[0.1, 0.5] of the roots refined
+    once; root box nx = ny = round(cbrt(roots)), nz = round(roots / nx^2);
+    a velocity grid drawn from `grids` on [-vmax, vmax]^3; sinusoidal
+    perturbations of rho, u, T (amplitudes U[0.05, 0.2], wave vectors in
+    {1, 2}^3); tau from Kn (hard sphere)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        target = math.exp(rng.uniform(math.log(cells_lo), math.log(cells_hi)))
+        refined = rng.random() < 0.5
+        frac = rng.uniform(0.1, 0.5) if refined else 0.0
+        roots = target / (1.0 + 7.0 * frac)
+        nx = max(1, int(round(roots ** (1.0 / 3.0))))
+        nz = max(1, int(round(roots / (nx * nx))))
+        nv = int(rng.choice(grids))
+        fseed = int(rng.integers(0, 2 ** 31))
+        base = (nx, nx, nz)
+        forest = (random_root_refinement(base, frac, fseed) if refined else uniform_forest(base, 0, 1.0 / nx))
+        out.append(Workload(f"batch{seed}_{i}", forest, (nv,) * 3, (-vmax,) * 3, (vmax,) * 3, SCHEME_UPWIND1,
+                            COLL_EXP, TAU_HS, kn, 0.5, 10, fields="sines", field_args={"seed": fseed}))
+    return out
+
+
 def workload(name: str) -> Workload:
     if name == "uniform16_v8_fp64":
         # 16^3 periodic cells, 8^3 velocities on [-4.5, 4.5]^3, rho = 1 + 0.1 sin 2 pi x

@@ -143,3 +143,38 @@ def test_muscl_solver_workspace_and_engine_host_only():
         D.lib().dvm_destroy_solver(h)
     fb = sizes[D.SCHEME_UPWIND1][0]
     assert sizes[D.SCHEME_MUSCL][1] == sizes[D.SCHEME_UPWIND1][1] + 3 * fb
+
+
+def test_batch_create_errors_host_only():
+    """dvm_batch_create groups host solvers and rejects what the batched
+    kernel does not do; no device call happens before dvm_batch_bind"""
+    import ctypes as C
+    m = D.Mesh(I.uniform_forest((1, 1, 1), 2))
+    hs = []
+    for nv, prec, scheme in [(8, D.PREC_FP32, D.SCHEME_UPWIND1), (12, D.PREC_FP32, D.SCHEME_UPWIND1),
+                             (8, D.PREC_FP64, D.SCHEME_UPWIND1), (8, D.PREC_FP32, D.SCHEME_MUSCL)]:
+        h = C.c_void_p()
+        p = D.make_params(nv, 4.5, precision=prec, scheme=scheme)
+        assert D.lib().dvm_create_solver(m.h, C.byref(p), C.byref(h)) == D.OK
+        hs.append(h)
+    arr = lambda *xs: (C.c_void_p * len(xs))(*[x.value for x in xs])
+    b = C.c_void_p()
+    assert D.lib().dvm_batch_create(arr(hs[0]), 0, 0.5, C.byref(b)) == D.ERR_ARG
+    assert D.lib().dvm_batch_create(arr(hs[0], hs[0]), 2, 0.5, C.byref(b)) == D.ERR_ARG
+    assert D.lib().dvm_batch_create(arr(hs[0], hs[2]), 2, 0.5, C.byref(b)) == D.ERR_UNSUPPORTED
+    assert D.lib().dvm_batch_create(arr(hs[0], hs[3]), 2, 0.5, C.byref(b)) == D.ERR_UNSUPPORTED
+    assert D.lib().dvm_batch_create(arr(hs[0], hs[1]), 2, -1.0, C.byref(b)) == D.ERR_ARG
+    assert D.lib().dvm_batch_create(arr(hs[0], hs[1]), 2, 0.5, C.byref(b)) == D.OK
+    nb = C.c_size_t(0)
+    assert D.lib().dvm_batch_workspace_bytes(b, C.byref(nb)) == D.OK and nb.value > 0
+    ng = C.c_int32(0)
+    assert D.lib().dvm_batch_info(b, -1, None, C.byref(ng), None, None, None, None, None, None) == D.OK
+    assert ng.value == 2  # two velocity grids
+    nh, ni, cells = C.c_int32(), C.c_int32(), C.c_int64()
+    assert D.lib().dvm_batch_info(b, 0, C.byref(nh), C.byref(ni), C.byref(cells), None, None, None, None,
+                                  None) == D.OK
+    assert (nh.value, ni.value, cells.value) == (6, 1, 64)  # larger grid first
+    assert D.lib().dvm_batch_step(b, 1, None) == D.ERR_WORKSPACE  # not bound
+    D.lib().dvm_destroy_batch(b)
+    for h in hs:
+        D.lib().dvm_destroy_solver(h)
