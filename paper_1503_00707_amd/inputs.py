@@ -179,9 +179,46 @@ def fields(recipe: str, x: np.ndarray, **kw) -> np.ndarray:
             k = rng.choice(ks, size=3)
             phi = rng.uniform(0, 2 * math.pi)
             out[v] = base[v] + a * np.sin(2 * math.pi * (x @ k) + phi)
+    elif recipe == "sensor_runs":   # rho, u_b, T = base + a sin(2 pi k.x + phi), a ~ U[0, amax], k in {0,1,2}^3 \ 0
+        rng = np.random.default_rng(kw["seed"])
+        amax = kw.get("amax", 0.3)
+        base = (1.0, 0.0, 0.0, 0.0, 1.0)
+        for v in range(5):
+            a = rng.uniform(0.0, amax)
+            k = np.zeros(3, np.int64)
+            while not k.any():
+                k = rng.integers(0, 3, size=3)
+            phi = rng.uniform(0, 2 * math.pi)
+            out[v] = base[v] + a * np.sin(2 * math.pi * (x @ k) + phi)
     else:
         raise ValueError(recipe)
     return out
+
+
+def sensor_run_tau(seed: int, lo: float = 0.01, hi: float = 1.0) -> float:
+    """Relaxation time of one sensor training run: log-uniform in [lo, hi]."""
+    rng = np.random.default_rng([seed, 7])
+    return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+MLP_IN, MLP_HIDDEN = 10, 64
+# parameter block: w1[64][10], b1[64], w2[64][64], b2[64], w3[64], b3, mean[10], std[10]
+MLP_WEIGHTS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+MLP_PARAMS = MLP_WEIGHTS + 2 * MLP_IN
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the 10-64-64-1 sensor network (uniform
+    Glorot bounds, zero biases, identity normalisation), float32 block."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(MLP_PARAMS, np.float32)
+    o = 0
+    for fan_in, fan_out in ((MLP_IN, MLP_HIDDEN), (MLP_HIDDEN, MLP_HIDDEN), (MLP_HIDDEN, 1)):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        p[o:o + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+        o += fan_in * fan_out + fan_out  # biases stay 0
+    p[MLP_WEIGHTS + MLP_IN:] = 1.0  # std
+    return p
 
 
 # ----------------------------------------------------------------------------
