@@ -86,6 +86,7 @@ extern "C" {
 typedef struct dvm_mesh dvm_mesh;
 typedef struct dvm_solver dvm_solver;
 typedef struct dvm_batch dvm_batch;
+typedef struct dvm_mlp dvm_mlp;
 
 typedef struct {
     int32_t base[3];          /* root cubes per axis, each >= 1 */
@@ -116,6 +117,7 @@ typedef struct {
     double inflow[5];         /* rho, ux, uy, uz, T of the inflow state */
     double t_wall;            /* diffuse-wall temperature */
     int32_t check_every;      /* global sums every k steps (0: never) */
+    int32_t hybrid;           /* 1: workspace for dvm_hybrid_step (masks, flux sums) */
 } dvm_params;
 
 typedef struct {
@@ -296,6 +298,74 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream);
 int dvm_batch_info(const dvm_batch *b, int32_t group, int32_t *nh, int32_t *n_inst, int64_t *n_cells,
                    int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store, double *tuned_ms);
 void dvm_destroy_batch(dvm_batch *b);
+
+/*
+ * Continuum-breakdown sensor, its training, and the kinetic/fluid hybrid step.
+ *
+ * Features (dvm_features; the sensor's input): per cell, from the moments
+ * buffer, x[c][10] = [ln rho, u/sqrt(T) (3), ln T, lambda |grad rho|/rho,
+ * lambda |grad u_b|/sqrt(T) (3), lambda |grad T|/T], lambda = tau sqrt(T),
+ * gradients by central differences over face-neighbour values (the mean of
+ * the four leaves of a FINER face) with centre distances h, 3h/4 (FINER),
+ * 3h/2 (COARSER); a domain face uses the cell's own value.  FP32 output,
+ * FP64 arithmetic.
+ * Labels (dvm_labels): r[c] = |f - Mt|_2 / |Mt|_2 over the velocity nodes of
+ * the current state, Mt the eq. 6 Maxwellian of the cell's own moments.
+ *
+ * The network 10-64-64-1 (exact GELU) lives in a caller-owned FP32 block of
+ * DVM_MLP_PARAMS floats: w1[64][10], b1[64], w2[64][64], b2[64], w3[64], b3,
+ * then the standardisation mean[10] and std[10] (x_std = (x - mean) / std).
+ * dvm_mlp_create / dvm_mlp_workspace_bytes / dvm_mlp_bind -- host object for
+ * batches of up to max_batch samples; the workspace (caller-owned, device)
+ * holds the Adam moments, the gradients and per-sample scratch.  Binding
+ * resets the Adam state (the caller's workspace must be zero-filled).
+ * dvm_mlp_set_normalization -- mean and standard deviation of x[n][10]
+ * (FP64, fixed order) into the parameter block.
+ * dvm_mlp_forward -- logits z[n] of raw features x[n][10]: mode 0 FP32
+ * (reference), mode 1 the matrix-core path (BF16 weights and activations,
+ * FP32 accumulation; the one the sensor uses).
+ * dvm_mlp_gradient -- loss and weight gradients of the class-weighted
+ * binary cross-entropy mean_i w_i [softplus(z_i) - y_i z_i], w_i = pos_weight
+ * for y_i = 1, else 1 (FP32 forward/backward, FP64 sums in sample order).
+ * dvm_mlp_adam -- one Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected)
+ * from the last gradients.  dvm_mlp_train_step = gradient + Adam.
+ * dvm_mlp_buffers -- device pointers of the last gradients [DVM_MLP_WEIGHTS]
+ * and loss (FP64), for inspection.
+ * dvm_sensor -- mask[c] = 1 (kinetic) or 0 (fluid) for the current moments:
+ * net != NULL: the network on the matrix cores, kinetic iff the logit > 0,
+ * score = probability; net == NULL: the gradient-length Knudsen number
+ * max(x[5..9]) against kappa, score = that number.  score may be NULL.
+ *
+ * dvm_hybrid_step -- n_steps steps with a frozen mask (device, n_cells
+ * bytes, 1 kinetic): kinetic cells run the fused step; fluid cells advance
+ * only their conserved moments U (held in the moments buffer) by the
+ * half-range fluxes of the discrete velocity set, U' = U - dt/h
+ * sum_faces (H_out(Mt(U)) + H_in(neighbour)), the neighbour's f when it is
+ * kinetic or Mt(U_nb) when it is fluid (section 2-3 of the paper: kinetic and
+ * continuum cells on one mesh).  A cell that becomes kinetic starts from
+ * Mt(U); one that becomes fluid keeps the moments of its f.  Cells touching
+ * a non-periodic domain face stay kinetic.  Needs params.hybrid = 1, the
+ * fused engine and first order (DVM_ERR_UNSUPPORTED otherwise).  With every
+ * cell kinetic it is dvm_step.  After hybrid steps the moments buffer is the
+ * state of fluid cells; dvm_moments recomputes from f (kinetic cells only).
+ */
+#define DVM_MLP_WEIGHTS 4929
+#define DVM_MLP_PARAMS 4949
+int dvm_features(dvm_solver *s, float *x, void *stream);
+int dvm_labels(dvm_solver *s, float *r, void *stream);
+int dvm_mlp_create(int64_t max_batch, dvm_mlp **out);
+int dvm_mlp_workspace_bytes(const dvm_mlp *net, size_t *bytes);
+int dvm_mlp_bind(dvm_mlp *net, float *params, void *ws);
+int dvm_mlp_set_normalization(dvm_mlp *net, const float *x, int64_t n, void *stream);
+int dvm_mlp_forward(const dvm_mlp *net, const float *x, int64_t n, int32_t mode, float *z, void *stream);
+int dvm_mlp_gradient(dvm_mlp *net, const float *x, const float *y, int64_t n, float pos_weight, void *stream);
+int dvm_mlp_adam(dvm_mlp *net, float lr, void *stream);
+int dvm_mlp_train_step(dvm_mlp *net, const float *x, const float *y, int64_t n, float lr, float pos_weight,
+                       void *stream);
+int dvm_mlp_buffers(const dvm_mlp *net, const float **grads, const double **loss);
+void dvm_destroy_mlp(dvm_mlp *net);
+int dvm_sensor(dvm_solver *s, const dvm_mlp *net, double kappa, uint8_t *mask, float *score, void *stream);
+int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double dt, double cfl, void *stream);
 
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);

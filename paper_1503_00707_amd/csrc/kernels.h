@@ -81,6 +81,34 @@ hipError_t launch_step_batch(bool fp64, const StepArgs *inst, const uint32_t *wg
                              int nh, const StepConfig &cfg, hipStream_t st);
 hipError_t launch_global_sums_batch(const SumArgs *inst, int n_inst, int n_part, hipStream_t st);
 
+// Sensor, training and hybrid step (sensor.hip).
+struct SensorArgsPub {
+    const double *mom;
+    const DevCell *cells;
+    int64_t n;
+    double h0;
+    int tau_mode;
+    double tau_or_kn;
+};
+struct HybArgsPub {
+    const uint8_t *mask;
+    uint8_t *prev;
+    double *flux;
+};
+constexpr int kMlpParams = 4949, kMlpWeights = 4929, kMlpRecord = 331, kFluxRecord = 66;
+hipError_t launch_features(const SensorArgsPub &a, float *x, hipStream_t st);
+hipError_t launch_labels(bool fp64, const void *f, float *r, int64_t n, const VelGrid &g, hipStream_t st);
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, int mode, float *z, hipStream_t st);
+hipError_t launch_sensor(const SensorArgsPub &a, const float *params, double kappa, uint8_t *mask, float *score,
+                         hipStream_t st);
+hipError_t launch_train(const float *params, const float *x, const float *y, int64_t n, float pos_weight,
+                        float *rec, double *loss_part, float *grad, double *loss, hipStream_t st);
+hipError_t launch_adam(float *params, float *m, float *v, const float *grad, float lr, float c1, float c2,
+                       hipStream_t st);
+hipError_t launch_norm_stats(const float *x, int64_t n, float *params, hipStream_t st);
+hipError_t launch_mask_eff(const uint8_t *in, uint8_t *out, const DevCell *cells, int64_t n, hipStream_t st);
+hipError_t launch_hybrid(bool fp64, const StepArgs &a, const HybArgsPub &h, hipStream_t st);
+
 // Deferred-collision engine (lazy_impl.h).
 struct UnitArgsPub {
     const void *f_in;

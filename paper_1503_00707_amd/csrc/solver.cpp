@@ -163,6 +163,9 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->muscl = p->scheme == DVM_SCHEME_MUSCL;
     s->off_face = o;
     if (s->muscl) o += 3 * s->f_bytes;
+    s->hybrid = p->hybrid != 0;
+    s->off_hyb = o;
+    if (s->hybrid) o += 2 * align256(size_t(s->n)) + align256(size_t(s->n) * kFluxRecord * 8);
     s->ws_bytes = o;
     if (nh == 12) s->sweep_k = 3;
     *out = s;
@@ -233,6 +236,9 @@ int dvm_upload(dvm_solver *s, void *stream) {
     }
     e = launch_identity(s->fp64, s->null_rec(), 1, s->nh, st);
     if (e != hipSuccess) return hip_fail(e, "identity record");
+    e = solver_reset_hybrid(s, st);
+    if (e != hipSuccess) return hip_fail(e, "hybrid masks");
+    s->hybrid_fluid = false;
     {
         int dev = 0;
         e = hipGetDevice(&dev);
@@ -264,6 +270,9 @@ int dvm_init_maxwellian(dvm_solver *s, const double *prim, void *stream) {
     s->relax_pending = false;
     e = ensure_lazy(s, S(stream));
     if (e != hipSuccess) return hip_fail(e, "init records");
+    e = solver_reset_hybrid(s, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "hybrid masks");
+    s->hybrid_fluid = false;
     s->steps = 0;
     return DVM_OK;
 }
@@ -281,6 +290,9 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     if (!s) return fail(DVM_ERR_ARG, "null solver");
     if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
     if (n_steps < 0) return fail(DVM_ERR_ARG, "n_steps < 0");
+    if (s->hybrid_fluid)
+        return fail(DVM_ERR_UNSUPPORTED, "fluid cells hold no f: continue with dvm_hybrid_step (an all-ones mask "
+                                         "turns every cell kinetic)");
     if (!(dt > 0)) {
         int rc = dvm_dt(s, cfl, &dt);
         if (rc) return rc;
@@ -393,6 +405,9 @@ int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, v
         s->relax_pending = false;
         e = ensure_lazy(s, S(stream));
         if (e != hipSuccess) return hip_fail(e, "records");
+        e = solver_reset_hybrid(s, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "hybrid masks");
+        s->hybrid_fluid = false;
     }
     return DVM_OK;
 }

@@ -35,6 +35,9 @@ struct dvm_solver {
     // workspace sections (byte offsets)
     size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
     size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
+    size_t off_hyb = 0;          // hybrid: effective mask [n], previous mask [n], flux sums [n][66]
+    bool hybrid = false;
+    bool hybrid_fluid = false;   // fluid cells may exist (their f is stale)
     bool muscl = false;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
@@ -71,4 +74,6 @@ hipError_t solver_make_plain(dvm_solver *s, hipStream_t st);
 // Kernel arguments of one fused step of size dt (f_in / f_out left NULL).
 StepArgs solver_step_args(const dvm_solver *s, double dt);
 double solver_max_speed_sum(const dvm_solver *s);
+// every cell kinetic again (a fresh state); no-op without the hybrid workspace
+hipError_t solver_reset_hybrid(dvm_solver *s, hipStream_t st);
 }  // namespace dvm

@@ -29,7 +29,11 @@ EXPORTED = [
     "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine",
     "dvm_batch_create", "dvm_batch_workspace_bytes", "dvm_batch_bind", "dvm_batch_step", "dvm_batch_tune",
     "dvm_batch_info", "dvm_destroy_batch",
+    "dvm_features", "dvm_labels", "dvm_mlp_create", "dvm_mlp_workspace_bytes", "dvm_mlp_bind",
+    "dvm_mlp_set_normalization", "dvm_mlp_forward", "dvm_mlp_gradient", "dvm_mlp_adam", "dvm_mlp_train_step",
+    "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
 ]
+MLP_WEIGHTS, MLP_PARAMS = 4929, 4949
 
 
 class DvmError(RuntimeError):
@@ -51,7 +55,8 @@ class MeshInfo(C.Structure):
 class Params(C.Structure):
     _fields_ = [("nv", C.c_int32), ("vmax", C.c_double * 3), ("precision", C.c_int32), ("scheme", C.c_int32),
                 ("collision", C.c_int32), ("tau_mode", C.c_int32), ("tau_or_kn", C.c_double),
-                ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32)]
+                ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32),
+                ("hybrid", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -107,6 +112,21 @@ def lib():
         L.dvm_batch_info.argtypes = [P, C.c_int32, P, P, P, P, P, P, P, P]
         L.dvm_destroy_batch.argtypes = [P]
         L.dvm_destroy_batch.restype = None
+        L.dvm_features.argtypes = [P, P, P]
+        L.dvm_labels.argtypes = [P, P, P]
+        L.dvm_mlp_create.argtypes = [C.c_int64, C.POINTER(P)]
+        L.dvm_mlp_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.dvm_mlp_bind.argtypes = [P, P, P]
+        L.dvm_mlp_set_normalization.argtypes = [P, P, C.c_int64, P]
+        L.dvm_mlp_forward.argtypes = [P, P, C.c_int64, C.c_int32, P, P]
+        L.dvm_mlp_gradient.argtypes = [P, P, P, C.c_int64, C.c_float, P]
+        L.dvm_mlp_adam.argtypes = [P, C.c_float, P]
+        L.dvm_mlp_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, C.c_float, P]
+        L.dvm_mlp_buffers.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+        L.dvm_destroy_mlp.argtypes = [P]
+        L.dvm_destroy_mlp.restype = None
+        L.dvm_sensor.argtypes = [P, P, C.c_double, P, P, P]
+        L.dvm_hybrid_step.argtypes = [P, P, C.c_int32, C.c_double, C.c_double, P]
         _LIB = L
     return _LIB
 
@@ -179,7 +199,8 @@ class Mesh:
 
 
 def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=COLL_EXP, tau_mode=TAU_CONST,
-                tau_or_kn=0.1, inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, check_every=0) -> Params:
+                tau_or_kn=0.1, inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, check_every=0,
+                hybrid=False) -> Params:
     p = Params()
     p.nv = int(nv)
     vm = (vmax,) * 3 if np.isscalar(vmax) else tuple(vmax)
@@ -191,6 +212,7 @@ def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=
         p.inflow[a] = float(inflow[a])
     p.t_wall = float(t_wall)
     p.check_every = int(check_every)
+    p.hybrid = int(bool(hybrid))
     return p
 
 
@@ -288,6 +310,32 @@ class Solver:
         _check(lib().dvm_tune_engine(self.h, int(engine), C.byref(prev)), "dvm_tune_engine")
         return int(prev.value)
 
+    def features(self):
+        """[n, 10] float32 sensor features of the current moments"""
+        out = self.torch.empty((self.n, 10), dtype=self.torch.float32, device="cuda")
+        _check(lib().dvm_features(self.h, out.data_ptr(), self.stream()), "dvm_features")
+        return out
+
+    def labels(self):
+        """[n] float32 |f - Mt| / |Mt| of the current state"""
+        out = self.torch.empty(self.n, dtype=self.torch.float32, device="cuda")
+        _check(lib().dvm_labels(self.h, out.data_ptr(), self.stream()), "dvm_labels")
+        return out
+
+    def sensor(self, net=None, kappa=0.0):
+        """(mask uint8 [n], score float32 [n]): network (net) or Kn_GLL > kappa"""
+        mask = self.torch.empty(self.n, dtype=self.torch.uint8, device="cuda")
+        score = self.torch.empty(self.n, dtype=self.torch.float32, device="cuda")
+        _check(lib().dvm_sensor(self.h, None if net is None else net.h, float(kappa), mask.data_ptr(),
+                                score.data_ptr(), self.stream()), "dvm_sensor")
+        return mask, score
+
+    def hybrid_step(self, mask, n=1, dt=0.0, cfl=0.5):
+        m = self.torch.as_tensor(mask).to(device="cuda", dtype=self.torch.uint8).contiguous()
+        self._mask = m
+        _check(lib().dvm_hybrid_step(self.h, m.data_ptr(), int(n), float(dt), float(cfl), self.stream()),
+               "dvm_hybrid_step")
+
     def get_shape(self):
         v = np.zeros(4, np.int32)
         _check(lib().dvm_tune_get(self.h, v[0:].ctypes.data, v[1:].ctypes.data, v[2:].ctypes.data,
@@ -347,6 +395,71 @@ class Batch:
         try:
             if getattr(self, "h", None):
                 lib().dvm_destroy_batch(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class MLP:
+    """The sensor network: parameters (torch float32 [MLP_PARAMS]) and the
+    training workspace (dvm_mlp_*)."""
+
+    def __init__(self, params, max_batch=4096):
+        import torch
+        self.torch = torch
+        self.params = torch.as_tensor(np.ascontiguousarray(params, np.float32)).to("cuda").contiguous()
+        assert self.params.numel() == MLP_PARAMS
+        h = C.c_void_p()
+        _check(lib().dvm_mlp_create(int(max_batch), C.byref(h)), "dvm_mlp_create")
+        self.h = h
+        nb = C.c_size_t(0)
+        _check(lib().dvm_mlp_workspace_bytes(h, C.byref(nb)), "dvm_mlp_workspace_bytes")
+        self.ws = torch.zeros(int(nb.value), dtype=torch.uint8, device="cuda")
+        _check(lib().dvm_mlp_bind(h, self.params.data_ptr(), self.ws.data_ptr()), "dvm_mlp_bind")
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def set_normalization(self, x):
+        x = x.contiguous()
+        _check(lib().dvm_mlp_set_normalization(self.h, x.data_ptr(), x.shape[0], self.stream()),
+               "dvm_mlp_set_normalization")
+
+    def forward(self, x, mode=1):
+        x = x.contiguous()
+        z = self.torch.empty(x.shape[0], dtype=self.torch.float32, device="cuda")
+        _check(lib().dvm_mlp_forward(self.h, x.data_ptr(), x.shape[0], int(mode), z.data_ptr(), self.stream()),
+               "dvm_mlp_forward")
+        return z
+
+    def gradient(self, x, y, pos_weight=1.0):
+        x, y = x.contiguous(), y.contiguous()
+        _check(lib().dvm_mlp_gradient(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], float(pos_weight),
+                                      self.stream()), "dvm_mlp_gradient")
+
+    def adam(self, lr):
+        _check(lib().dvm_mlp_adam(self.h, float(lr), self.stream()), "dvm_mlp_adam")
+
+    def train_step(self, x, y, lr, pos_weight=1.0):
+        x, y = x.contiguous(), y.contiguous()
+        _check(lib().dvm_mlp_train_step(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], float(lr),
+                                        float(pos_weight), self.stream()), "dvm_mlp_train_step")
+
+    def grads_and_loss(self):
+        """(gradient float32 [MLP_WEIGHTS], loss) of the last gradient call (synchronises)"""
+        g, l = C.c_void_p(), C.c_void_p()
+        _check(lib().dvm_mlp_buffers(self.h, C.byref(g), C.byref(l)), "dvm_mlp_buffers")
+        self.torch.cuda.synchronize()
+        base = self.ws.data_ptr()
+        go, lo = g.value - base, l.value - base
+        grads = self.ws[go:go + 4 * MLP_WEIGHTS].view(self.torch.float32).clone()
+        loss = float(self.ws[lo:lo + 8].view(self.torch.float64).item())
+        return grads, loss
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().dvm_destroy_mlp(self.h)
                 self.h = None
         except Exception:
             pass

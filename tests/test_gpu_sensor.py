@@ -1,0 +1,201 @@
+"""The sensor, its training kernels and the hybrid step through the C
+interface, against the FP64 oracle of oracle/sensor.py on the same seeded
+inputs (never on values produced by the HIP path)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import sensor as S
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+from tests.gpu_common import balanced
+
+pytestmark = pytest.mark.gpu
+
+NV, VLO, VHI = (8, 8, 8), (-4.5,) * 3, (4.5,) * 3
+
+
+def _case(seed=3, tau=0.05, tau_mode=I.TAU_CONST):
+    f = balanced(I.random_forest(seed, (2, 2, 2), 2, 0.3))
+    return f
+
+
+def _pair(f, steps, prec=D.PREC_FP64, tau=0.05, tau_mode=I.TAU_CONST, hybrid=False, fseed=31):
+    """the same seeded flow advanced by the oracle and by the library"""
+    om = O.Mesh(f)
+    ot = om.tables()
+    op = O.make_params(NV, VLO, VHI, tau_mode=tau_mode, tau_or_kn=tau)
+    os_ = O.Solver(om, op)
+    prim_o = I.fields("sines", I.leaf_centres(f)[ot["input"]], seed=fseed)
+    os_.init_maxwellian(prim_o)
+    dt = os_.dt_cfl(0.5)
+    if steps:
+        os_.step(dt, steps)
+    dm = D.Mesh(f)
+    dt_ = dm.tables()
+    p = D.make_params(8, 4.5, precision=prec, tau_mode=tau_mode, tau_or_kn=tau, hybrid=hybrid)
+    s = D.Solver(dm, p)
+    s.init_maxwellian(I.fields("sines", I.leaf_centres(f)[dt_["input"]], seed=fseed))
+    if steps:
+        s.step(steps, dt=dt)
+    return om, ot, op, os_, dm, s, dt
+
+
+def test_features_and_labels_match_oracle():
+    import torch
+    f = _case()
+    om, ot, op, os_, dm, s, dt = _pair(f, 4)
+    xo = S.features(os_.moments(), ot, f.h0, 0, 0.05)
+    xg = s.features().double().cpu().numpy()
+    scale = np.abs(xo).max(axis=0) + 1e-30
+    assert np.all(np.abs(xg - xo).max(axis=0) <= 1e-6 * scale)
+    ro = S.labels(os_.get_f(), NV, VLO, VHI)
+    rg = s.labels().double().cpu().numpy()
+    assert np.abs(rg - ro).max() <= 1e-6 * ro.max() + 1e-12
+    torch.cuda.synchronize()
+
+
+def _net_and_data(seed=1, n=300):
+    rng = np.random.default_rng(seed)
+    p = I.mlp_init(seed).astype(np.float32)
+    p[:I.MLP_WEIGHTS] += rng.normal(0, 0.05, I.MLP_WEIGHTS).astype(np.float32)
+    p[I.MLP_WEIGHTS:I.MLP_WEIGHTS + 10] = rng.normal(0, 0.3, 10)
+    p[I.MLP_WEIGHTS + 10:] = rng.uniform(0.5, 2.0, 10)
+    x = rng.normal(0, 1.0, (n, 10)).astype(np.float32)
+    y = (rng.random(n) < 0.3).astype(np.float32)
+    return p, x, y
+
+
+def test_mlp_forward_fp32_and_matrix_cores_match_oracle():
+    import torch
+    p, x, y = _net_and_data(n=333)
+    net = D.MLP(p, max_batch=512)
+    xt = torch.as_tensor(x).cuda()
+    zo, _ = S.mlp_forward(p.astype(np.float64), x.astype(np.float64))
+    z32 = net.forward(xt, mode=0).double().cpu().numpy()
+    zmf = net.forward(xt, mode=1).double().cpu().numpy()
+    scale = np.abs(zo).max()
+    assert np.abs(z32 - zo).max() <= 1e-5 * scale
+    assert np.abs(zmf - zo).max() <= 2e-2 * scale
+
+
+def test_mlp_gradient_and_adam_match_oracle():
+    import torch
+    p, x, y = _net_and_data(seed=2, n=257)
+    net = D.MLP(p, max_batch=512)
+    xt, yt = torch.as_tensor(x).cuda(), torch.as_tensor(y).cuda()
+    net.gradient(xt, yt, pos_weight=3.0)
+    g, loss = net.grads_and_loss()
+    lo, go = S.loss_and_grad(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64), 3.0)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    assert np.abs(g.double().cpu().numpy() - go).max() <= 1e-5 * np.abs(go).max()
+    # three Adam steps on the same batch
+    w = p.astype(np.float64).copy()
+    m = np.zeros(I.MLP_WEIGHTS)
+    v = np.zeros(I.MLP_WEIGHTS)
+    net = D.MLP(p, max_batch=512)
+    for t in range(1, 4):
+        net.train_step(xt, yt, lr=1e-2, pos_weight=3.0)
+        _, gw = S.loss_and_grad(w, x.astype(np.float64), y.astype(np.float64), 3.0)
+        w[:I.MLP_WEIGHTS], m, v = S.adam_step(w[:I.MLP_WEIGHTS], gw, m, v, t, 1e-2)
+    got = net.params.double().cpu().numpy()
+    # Adam moves every weight by about lr per step whatever |g| is, so an FP32
+    # update differs from the FP64 one relative to lr (most where |g| ~ eps)
+    assert np.abs(got[:I.MLP_WEIGHTS] - w[:I.MLP_WEIGHTS]).max() <= 1e-3 * 1e-2 * 3
+    assert np.array_equal(got[I.MLP_WEIGHTS:], p[I.MLP_WEIGHTS:].astype(np.float64))
+
+
+def test_normalization_statistics():
+    import torch
+    p, x, _ = _net_and_data(seed=4, n=1000)
+    x = x * np.arange(1, 11, dtype=np.float32) + np.arange(10, dtype=np.float32)
+    net = D.MLP(p, max_batch=16)
+    net.set_normalization(torch.as_tensor(x).cuda())
+    got = net.params.double().cpu().numpy()
+    xd = x.astype(np.float64)
+    assert np.allclose(got[I.MLP_WEIGHTS:I.MLP_WEIGHTS + 10], xd.mean(0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(got[I.MLP_WEIGHTS + 10:], xd.std(0), rtol=1e-6)
+
+
+def test_sensor_masks_match_oracle():
+    import torch
+    f = _case(seed=5)
+    om, ot, op, os_, dm, s, dt = _pair(f, 3, tau=0.2)
+    xo = S.features(os_.moments(), ot, f.h0, 0, 0.2)
+    kappa = float(np.median(S.kn_gll(xo)))
+    mask, score = s.sensor(None, kappa)
+    kg = S.kn_gll(xo)
+    sure = np.abs(kg - kappa) > 1e-6 * kappa
+    assert np.array_equal(mask.cpu().numpy()[sure], (kg > kappa)[sure].astype(np.uint8))
+    p, _, _ = _net_and_data(seed=6)
+    p[I.MLP_WEIGHTS:I.MLP_WEIGHTS + 10] = xo.mean(0)
+    p[I.MLP_WEIGHTS + 10:] = xo.std(0) + 1e-6
+    net = D.MLP(p, max_batch=16)
+    mask, prob = s.sensor(net)
+    zo, _ = S.mlp_forward(p.astype(np.float64), xo)
+    sure = np.abs(zo) > 0.05 * np.abs(zo).max()
+    assert sure.sum() > 10
+    assert np.array_equal(mask.cpu().numpy()[sure], (zo > 0)[sure].astype(np.uint8))
+    torch.cuda.synchronize()
+
+
+# --- hybrid step ----------------------------------------------------------
+
+def test_hybrid_all_kinetic_is_plain_step_bitwise():
+    import torch
+    f = _case(seed=7)
+    _, _, _, _, dm, s1, dt = _pair(f, 0, hybrid=True)
+    _, _, _, _, dm2, s2, _ = _pair(f, 0)
+    s1.hybrid_step(np.ones(s1.n, np.uint8), n=5, dt=dt)
+    s2.step(5, dt=dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(s1.f_canonical().cpu().numpy(), s2.f_canonical().cpu().numpy())
+    assert np.array_equal(s1.mom.cpu().numpy(), s2.mom.cpu().numpy())
+
+
+@pytest.mark.parametrize("frac", [0.3, 0.7])
+def test_hybrid_mixed_mask_matches_oracle_fp64(frac):
+    import torch
+    f = _case(seed=8)
+    om, ot, op, os_, dm, s, dt = _pair(f, 0, hybrid=True)
+    rng = np.random.default_rng(int(frac * 10))
+    h = S.Hybrid(os_, op, NV, VLO, VHI)
+    for rep in range(2):
+        mask = rng.random(s.n) < frac  # same cell order on both sides (Morton)
+        h.set_mask(mask)
+        for _ in range(3):
+            h.step(dt)
+        s.hybrid_step(mask.astype(np.uint8), n=3, dt=dt)
+    torch.cuda.synchronize()
+    Ug = s.mom.cpu().numpy()
+    scale = np.abs(h.U).max(axis=1)
+    assert np.all(np.abs(Ug - h.U).max(axis=1) <= 1e-12 * scale)
+    fg = s.f_canonical().cpu().numpy()
+    kin = h.kinetic
+    assert np.abs(fg[kin] - h.f[kin]).max() <= 1e-12 * np.abs(h.f[kin]).max()
+
+
+def test_hybrid_all_fluid_uniform_state_stationary_and_conservative():
+    import torch
+    f = I.uniform_forest((2, 2, 2), 1)
+    dm = D.Mesh(f)
+    p = D.make_params(8, 4.5, precision=D.PREC_FP64, tau_or_kn=0.1, hybrid=True)
+    s = D.Solver(dm, p)
+    s.init_maxwellian(np.tile(np.array([[1.1], [0.3], [-0.2], [0.1], [0.95]]), (1, s.n)))
+    U0 = s.mom.cpu().numpy().copy()
+    s.hybrid_step(np.zeros(s.n, np.uint8), n=4)
+    torch.cuda.synchronize()
+    assert np.abs(s.mom.cpu().numpy() - U0).max() <= 1e-14 * np.abs(U0).max()
+    # a non-uniform flow with a mixed mask conserves the global sums
+    g = _case(seed=9)
+    _, _, _, _, dm2, s2, dt = _pair(g, 0, hybrid=True)
+    rc, tot0, _, _ = s2.check()
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        s2.hybrid_step((rng.random(s2.n) < 0.5).astype(np.uint8), n=2, dt=dt)
+    rc, tot, bad, _ = s2.check()
+    assert rc == 0 and not bad
+    scale = np.array([tot0[0]] * 4 + [tot0[4]])
+    assert np.all(np.abs(tot - tot0) <= 1e-13 * scale)
