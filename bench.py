@@ -27,6 +27,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DVM cell-velocity updates/s + % HBM roofline, FP64/FP32/hybrid, same error"
 HBM_PEAK_GBS = 8000.0
+# sources that define the fused step kernel: HBM counters recorded under
+# profiles/ count only while these are unchanged
+KERNEL_SOURCES = ["paper_1503_00707_amd/csrc/step_impl.h", "paper_1503_00707_amd/csrc/kernels.h",
+                  "paper_1503_00707_amd/csrc/kernels_f32.hip"]
+TRAFFIC_PROFILE = "profiles/k_step_fused_octree64_v24_p40_fp32.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_launch_bytes):
+    """HBM bytes per launch from the committed counter profile, if it was
+    taken on the current kernel source (else None)"""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            t = json.loads(line.split(":", 1)[1])
+            if t.get("source_sha256") != kernel_source_hash():
+                return None
+            return dict(read_bytes=t["read_bytes"], write_bytes=t["write_bytes"],
+                        total_bytes=t["read_bytes"] + t["write_bytes"],
+                        vs_algorithmic=(t["read_bytes"] + t["write_bytes"]) / n_launch_bytes,
+                        source=TRAFFIC_PROFILE)
+    return None
 
 
 def log(msg):
@@ -275,7 +307,7 @@ def main():
                    "pct_hbm_roofline_whole_step": 100.0 * (2 * r["fbytes"] * r["n"] * r["nv"]) / (ms / 1e3) / 8e12},
         "roofline": {"bound": "hbm", "kernel": "k_step (fused transport+moments+Maxwellian+BGK)",
                      "achieved": r["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r["achieved"] / HBM_PEAK_GBS, "traffic": measured_traffic(r["alg_bytes"]),
                      "kernel_ms_mean": float(np.mean(r["k_ms"])), "algorithmic_bytes_per_launch": r["alg_bytes"]},
         "conservation_drift_rel": {"mass": float(r["drift"][0]), "energy": float(r["drift"][4])},
         "status": int(r["rc"]),

@@ -32,8 +32,13 @@ SensorArgsPub sensor_args(const dvm_solver *s) {
 
 uint8_t *hyb_mask(const dvm_solver *s) { return reinterpret_cast<uint8_t *>(s->ws + s->off_hyb); }
 uint8_t *hyb_prev(const dvm_solver *s) { return hyb_mask(s) + align256(size_t(s->n)); }
+uint8_t *hyb_rows(const dvm_solver *s) { return hyb_mask(s) + 2 * align256(size_t(s->n)); }
 double *hyb_flux(const dvm_solver *s) {
-    return reinterpret_cast<double *>(s->ws + s->off_hyb + 2 * align256(size_t(s->n)));
+    return reinterpret_cast<double *>(s->ws + s->off_hyb + 3 * align256(size_t(s->n)));
+}
+double *hyb_face(const dvm_solver *s) {
+    return reinterpret_cast<double *>(reinterpret_cast<char *>(hyb_flux(s)) +
+                                      align256(size_t(s->n) * kFluxRecord * 8));
 }
 
 int check_net(const dvm_mlp *net, int64_t n) {
@@ -182,7 +187,7 @@ int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double 
     hipError_t e = solver_make_plain(s, st);
     if (e == hipSuccess) e = launch_mask_eff(mask, hyb_mask(s), s->tables, s->n, st);
     if (e != hipSuccess) return hip_fail(e, "hybrid mask");
-    const HybArgsPub h{hyb_mask(s), hyb_prev(s), hyb_flux(s)};
+    const HybArgsPub h{hyb_mask(s), hyb_prev(s), hyb_rows(s), hyb_flux(s), hyb_face(s)};
     for (int it = 0; it < n_steps; ++it) {
         StepArgs a = solver_step_args(s, dt);
         a.f_in = s->f[s->cur];

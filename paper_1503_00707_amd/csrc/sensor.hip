@@ -10,6 +10,7 @@ static_assert(sizeof(SensorArgsPub) == sizeof(impl::FeatArgs), "argument layout"
 static_assert(sizeof(HybArgsPub) == sizeof(impl::HybArgs), "argument layout");
 static_assert(kMlpParams == impl::kParams && kMlpWeights == impl::kWeights, "parameter block");
 static_assert(kMlpRecord == impl::kRec && kFluxRecord == impl::kFluxRec, "scratch records");
+static_assert(kFaceRecord == 6 * 5, "face flux records");
 
 static impl::FeatArgs feat(const SensorArgsPub &a) {
     impl::FeatArgs f;

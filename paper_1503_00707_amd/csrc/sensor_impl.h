@@ -472,7 +472,9 @@ constexpr int kFluxRec = 66;  // per axis: full A[3], B[3]; + half A[4], B[4]; -
 struct HybArgs {
     const uint8_t *mask;  // effective mask (1 kinetic)
     uint8_t *prev;        // mask of the previous hybrid step
+    uint8_t *rows;        // 1: write Mt(U) into the state buffer before the step
     double *flux;         // [n][kFluxRec] separable sums of fluid cells' Maxwellians
+    double *face;         // [n][6][5] outgoing half-range fluxes of kinetic cells next to fluid ones
 };
 
 // mask | (cell touches a non-periodic domain face): those cells stay kinetic
@@ -484,15 +486,57 @@ __global__ __launch_bounds__(256) void k_mask_eff(const uint8_t *in, uint8_t *ou
     out[c] = m;
 }
 
-// Per cell before a hybrid step: fluid cells get their flux record; fluid
-// cells next to a kinetic cell and cells turning kinetic write Mt(U) into
-// the state buffer; the previous mask is updated.
-template <typename F, int NH, int T>
-__global__ __launch_bounds__(T) void k_hybrid_prep(StepArgs a, HybArgs h) {
-    constexpr int N = 2 * NH;
-    constexpr int64_t NV = 8 * NH * NH * NH;
-    __shared__ StepSmem<F, NH, T> sm;
-    const int64_t c = blockIdx.x, n = a.n_cells;
+// Corrected Maxwellian of conserved moments U by one thread (the same
+// construction as maxwell_solve): C and the coefficients d of the centred
+// basis.  Returns false for a non-physical state.
+__device__ inline bool maxwell_serial(const double U[5], const VelGrid &g, double u[3], double &sT, double &C,
+                                      double d[5]) {
+    const int nh = g.nh, N = 2 * nh;
+    const double rho = U[0];
+    for (int b = 0; b < 3; ++b) u[b] = U[1 + b] / rho;
+    const double Tt = (2.0 * U[4] / rho - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
+    if (!(rho > 0.0) || !(Tt > 0.0)) return false;
+    sT = sqrt(Tt);
+    double S[15];
+    for (int b = 0; b < 3; ++b) {
+        double p[5] = {0, 0, 0, 0, 0};
+        const double dvb = b == 0 ? g.dv[0] : b == 1 ? g.dv[1] : g.dv[2];
+        const double ub = b == 0 ? u[0] : b == 1 ? u[1] : u[2];
+        for (int k = 0; k < N; ++k) {
+            const double ck = ((double(k - nh) + 0.5) * dvb - ub) / sT;
+            double t = exp(-0.5 * ck * ck);
+            for (int q = 0; q < 5; ++q) {
+                p[q] += t;
+                t *= ck;
+            }
+        }
+        for (int q = 0; q < 5; ++q) S[5 * b + q] = p[q] * dvb;
+    }
+    const double x2 = 6.283185307179586476925286766559 * Tt;
+    C = rho / (x2 * sqrt(x2));
+    double A[5][6];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 6; ++j) {
+            if (j < 5) A[i][j] = gram_entry(i, j, &S[0], &S[5], &S[10]);
+            else A[i][j] = (i == 0 ? 1.0 : i == 4 ? 3.0 : 0.0) * (rho / C) - gram_entry(i, 0, &S[0], &S[5], &S[10]);
+        }
+    for (int k = 0; k < 5; ++k)
+        for (int i = 0; i < 5; ++i) {
+            if (i == k) continue;
+            const double r = A[i][k] / A[k][k];
+            for (int j = 0; j < 6; ++j) A[i][j] -= r * A[k][j];
+        }
+    for (int i = 0; i < 5; ++i) d[i] = A[i][5] / A[i][i];
+    return true;
+}
+
+// Per cell, one thread: fluid cells get the separable sums of their
+// Maxwellian; the cells whose state buffer row must hold Mt(U) this step
+// are flagged (fluid cells next to a kinetic one, cells turning kinetic);
+// the previous mask is updated.
+__global__ __launch_bounds__(256) void k_fluid_state(StepArgs a, HybArgs h) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x, n = a.n_cells;
+    if (c >= n) return;
     const int m = h.mask[c], pm = h.prev[c];
     const DevCell &cell = a.cells[c];
     bool kin_nb = false;
@@ -501,12 +545,52 @@ __global__ __launch_bounds__(T) void k_hybrid_prep(StepArgs a, HybArgs h) {
         const int k = ty == DVM_FACE_FINER ? 4 : (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) ? 1 : 0;
         for (int q = 0; q < k; ++q) kin_nb |= h.mask[cell.nbr[f][q]] != 0;
     }
-    const bool write_row = (m == 0 && kin_nb) || (m == 1 && pm == 0);
-    if (m == 1 && !write_row) {
-        __syncthreads();
-        if (threadIdx.x == 0) h.prev[c] = 1;
+    h.rows[c] = uint8_t((m == 0 && kin_nb) || (m == 1 && pm == 0));
+    h.prev[c] = uint8_t(m);
+    if (m) return;
+    double U[5], u[3], sT, C, d[5];
+    for (int x = 0; x < 5; ++x) U[x] = a.mom[x * n + c];
+    if (!maxwell_serial(U, a.g, u, sT, C, d)) {
+        *a.flag = 1;
         return;
     }
+    const int nh = a.g.nh, N = 2 * nh;
+    double *R = h.flux + c * kFluxRec;
+    for (int b = 0; b < 3; ++b) {
+        double acc[22];
+        for (int t = 0; t < 22; ++t) acc[t] = 0.0;
+        const double dvb = b == 0 ? a.g.dv[0] : b == 1 ? a.g.dv[1] : a.g.dv[2];
+        const double ub = b == 0 ? u[0] : b == 1 ? u[1] : u[2];
+        const double db = b == 0 ? d[1] : b == 1 ? d[2] : d[3];
+        for (int k = 0; k < N; ++k) {
+            const double xi = (double(k - nh) + 0.5) * dvb;
+            const double cc = (xi - ub) / sT;
+            const double gk = exp(-0.5 * cc * cc);
+            const double G = b == 0 ? gk * C : gk;
+            const double P = (b == 0 ? 1.0 + d[0] : 0.0) + db * cc + d[4] * cc * cc;
+            const int hb = k >= nh ? 6 : 14;
+            double xp = 1.0;
+            for (int p = 0; p < 4; ++p) {
+                if (p < 3) {
+                    acc[p] += xp * G;
+                    acc[3 + p] += xp * G * P;
+                }
+                acc[hb + p] += xp * G;
+                acc[hb + 4 + p] += xp * G * P;
+                xp *= xi;
+            }
+        }
+        for (int t = 0; t < 22; ++t) R[b * 22 + t] = acc[t];
+    }
+}
+
+// Mt(U) rows of the flagged cells (one workgroup per cell, others exit).
+template <typename F, int NH, int T>
+__global__ __launch_bounds__(T) void k_hybrid_rows(StepArgs a, HybArgs h) {
+    constexpr int64_t NV = 8 * NH * NH * NH;
+    __shared__ MaxwellSmem<F, NH> sm;
+    const int64_t c = blockIdx.x, n = a.n_cells;
+    if (!h.rows[c]) return;
     const double rho = a.mom[c];
     const double u[3] = {a.mom[n + c] / rho, a.mom[2 * n + c] / rho, a.mom[3 * n + c] / rho};
     const double Tt = (2.0 * a.mom[4 * n + c] / rho - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
@@ -514,41 +598,12 @@ __global__ __launch_bounds__(T) void k_hybrid_prep(StepArgs a, HybArgs h) {
         if (threadIdx.x == 0) *a.flag = 1;
         return;
     }
-    maxwell_tables<F, NH, T>(sm.mx, rho, u, Tt, 1.0, a.g);
-    if (write_row) {
-        F zero[8][Lane<NH, T>::S];
-        for (int q = 0; q < Lane<NH, T>::S; ++q)
-            for (int o = 0; o < 8; ++o) zero[o][q] = F(0);
-        const Rsrc out = rsrc(static_cast<const F *>(a.f_in) + c * NV, uint32_t(NV * sizeof(F)));
-        relax_store<F, NH, T, false>(sm.mx, zero, F(0), out);
-    }
-    if (m == 0 && threadIdx.x < 3) {
-        // separable sums of the FP64 Maxwellian: per axis over all nodes and
-        // over the positive / negative halves, A[p] = sum xi^p G, B[p] = sum xi^p G P
-        const int b = threadIdx.x;
-        double *R = h.flux + c * kFluxRec + b * 22;
-        for (int t = 0; t < 22; ++t) R[t] = 0.0;
-        for (int k = 0; k < N; ++k) {
-            const double xi = (double(k - NH) + 0.5) * a.g.dv[b];
-            const double cc = sm.mx.c[b][k];
-            const double G = b == 0 ? sm.mx.g[b][k] * sm.mx.C : sm.mx.g[b][k];
-            const double Pk = b == 0 ? 1.0 + sm.mx.d[0] + sm.mx.d[1] * cc + sm.mx.d[4] * cc * cc
-                                     : sm.mx.d[1 + b] * cc + sm.mx.d[4] * cc * cc;
-            double xp = 1.0;
-            for (int p = 0; p < 4; ++p) {
-                if (p < 3) {
-                    R[p] += xp * G;
-                    R[3 + p] += xp * G * Pk;
-                }
-                const int hb = k >= NH ? 6 : 14;
-                R[hb + p] += xp * G;
-                R[hb + 4 + p] += xp * G * Pk;
-                xp *= xi;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) h.prev[c] = uint8_t(m);
+    maxwell_tables<F, NH, T>(sm, rho, u, Tt, 1.0, a.g);
+    F zero[8][Lane<NH, T>::S];
+    for (int q = 0; q < Lane<NH, T>::S; ++q)
+        for (int o = 0; o < 8; ++o) zero[o][q] = F(0);
+    const Rsrc out = rsrc(static_cast<const F *>(a.f_in) + c * NV, uint32_t(NV * sizeof(F)));
+    relax_store<F, NH, T, false>(sm, zero, F(0), out);
 }
 
 // sum over the tensor grid of prod_a xi_a^p[a] Mt, the normal axis b summed
@@ -573,15 +628,68 @@ __device__ __forceinline__ void sep_flux(const double *R, int b, int hs, double 
               sep_moment(R, b, hs, px, py, pz + 2));
 }
 
-// Fluid update of cell c by the whole workgroup.
-template <typename F, int NH, int T>
-__device__ void fluid_cell(const StepArgs &a, const HybArgs &h, int64_t c, double *red) {
-    using L = Lane<NH, T>;
-    constexpr int S = L::S;
-    constexpr int B = L::B;
-    constexpr int64_t NV = 8 * B;
-    const L ln;
-    const int64_t n = a.n_cells;
+// Kinetic cells next to fluid ones: the half-range flux of their own f
+// through each such face, w sum_{leaving} xi_b psi f (signed xi_b), before
+// the transport overwrites f.
+struct HybHook {
+    HybArgs h;
+    template <typename F, int NH, int T>
+    __device__ __forceinline__ void apply(const StepArgs &a, const CellView &cell, int64_t c,
+                                          const Regs<F, NH, T> &fo, double *red) const {
+        using L = Lane<NH, T>;
+        constexpr int S = L::S;
+        const L ln;
+#pragma nounroll
+        for (int f = 0; f < 6; ++f) {
+            const int ty = cell.type_rt(f);
+            const int k = ty == DVM_FACE_FINER ? 4 : (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) ? 1 : 0;
+            bool fluid_nb = false;
+            for (int q = 0; q < k; ++q) fluid_nb |= h.mask[cell.nbr_rt(f, q)] == 0;
+            if (!fluid_nb) continue;
+            const int b = f >> 1, side = f & 1;
+            double v[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (!ln.ok(q)) continue;
+                int a3[3];
+                ln.axes(q, a3[0], a3[1], a3[2]);
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const int sx = o >> 2, sy = (o >> 1) & 1, sz = o & 1;
+                    const int sbb = b == 0 ? sx : b == 1 ? sy : sz;
+                    if (sbb != side) continue;  // not leaving through f
+                    const double x0 = (sx ? 1.0 : -1.0) * (a3[0] + 0.5) * a.g.dv[0];
+                    const double x1 = (sy ? 1.0 : -1.0) * (a3[1] + 0.5) * a.g.dv[1];
+                    const double x2 = (sz ? 1.0 : -1.0) * (a3[2] + 0.5) * a.g.dv[2];
+                    const double xn = (b == 0 ? x0 : b == 1 ? x1 : x2) * double(fo[o][q]);
+                    v[0] += xn;
+                    v[1] += xn * x0;
+                    v[2] += xn * x1;
+                    v[3] += xn * x2;
+                    v[4] += 0.5 * xn * ((x0 * x0 + x1 * x1) + x2 * x2);
+                }
+            }
+            block_sum<T, 5>(v, red);
+            if (threadIdx.x == 0)
+                for (int x = 0; x < 5; ++x) h.face[(c * 6 + f) * 5 + x] = a.g.w * v[x];
+        }
+    }
+};
+
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step_hybrid(StepArgs a,
+                                                                                               HybArgs h) {
+    __shared__ StepSmem<F, NH, T> sm;
+    const int64_t c = blockIdx.x;
+    if (!h.mask[c]) return;  // fluid cells: k_fluid_update
+    const HybHook hook{h};
+    step_cell<F, NH, T, FENCE, NT, false, HybHook>(a, c, sm, hook);
+}
+
+// Fluid cells, one thread each: U' = U - dt/h sum_faces (H_out + H_in).
+__global__ __launch_bounds__(256) void k_fluid_update(StepArgs a, HybArgs h) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x, n = a.n_cells;
+    if (c >= n || h.mask[c]) return;
     const DevCell &cell = a.cells[c];
     const double hc = a.h0 / double(1 << cell.level);
     const double w = a.g.w;
@@ -590,7 +698,6 @@ __device__ void fluid_cell(const StepArgs &a, const HybArgs &h, int64_t c, doubl
         const int b = f >> 1, side = f & 1;
         const double sg = side ? 1.0 : -1.0;  // outward normal along b
         const int ty = cell.type[f];
-        // leaving through f: xi_b of the sign of the normal (own Maxwellian)
         double hout[5];
         sep_flux(h.flux + c * kFluxRec, b, side ? 6 : 14, w, hout);
         const int nk = ty == DVM_FACE_FINER ? 4 : 1;
@@ -601,55 +708,19 @@ __device__ void fluid_cell(const StepArgs &a, const HybArgs &h, int64_t c, doubl
             if (h.mask[nb] == 0) {
                 sep_flux(h.flux + nb * kFluxRec, b, side ? 14 : 6, w, t);
             } else {
-                // entering from a kinetic neighbour: its half row, xi_b of the opposite sign
-                const F *row = static_cast<const F *>(a.f_in) + nb * NV;
-                double v[5] = {0, 0, 0, 0, 0};
-                for (int q = 0; q < S; ++q) {
-                    if (!ln.ok(q)) continue;
-                    int a3[3];
-                    ln.axes(q, a3[0], a3[1], a3[2]);
-#pragma unroll
-                    for (int o = 0; o < 8; ++o) {
-                        const int sx = o >> 2, sy = (o >> 1) & 1, sz = o & 1;
-                        const int sbb = b == 0 ? sx : b == 1 ? sy : sz;
-                        if (sbb == side) continue;  // leaving the neighbour away from c
-                        const double x0 = (sx ? 1.0 : -1.0) * (a3[0] + 0.5) * a.g.dv[0];
-                        const double x1 = (sy ? 1.0 : -1.0) * (a3[1] + 0.5) * a.g.dv[1];
-                        const double x2 = (sz ? 1.0 : -1.0) * (a3[2] + 0.5) * a.g.dv[2];
-                        const double fv = double(row[o * B + ln.slot(q)]);
-                        const double xn = (b == 0 ? x0 : b == 1 ? x1 : x2) * fv;
-                        v[0] += xn;
-                        v[1] += xn * x0;
-                        v[2] += xn * x1;
-                        v[3] += xn * x2;
-                        v[4] += 0.5 * xn * ((x0 * x0 + x1 * x1) + x2 * x2);
-                    }
-                }
-                block_sum<T, 5>(v, red);
-                for (int x = 0; x < 5; ++x) t[x] = w * v[x];
+                const double *q = h.face + (nb * 6 + (f ^ 1)) * 5;  // leaving nb towards c
+                for (int x = 0; x < 5; ++x) t[x] = q[x];
             }
             for (int x = 0; x < 5; ++x) hin[x] += t[x];
         }
         for (int x = 0; x < 5; ++x) acc[x] += sg * (hout[x] + hin[x] / double(nk));
     }
-    if (threadIdx.x == 0) {
-        const double dth = a.dt / hc;
-        double U[5];
-        for (int x = 0; x < 5; ++x) U[x] = a.mom[x * n + c] - dth * acc[x];
-        for (int x = 0; x < 5; ++x) a.mom[x * n + c] = U[x];
-        const double rho = U[0];
-        const double k2 = (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / rho;
-        if (!(rho > 0.0) || !(2.0 * U[4] - k2 > 0.0)) *a.flag = 1;
-    }
-}
-
-template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step_hybrid(StepArgs a,
-                                                                                               HybArgs h) {
-    __shared__ StepSmem<F, NH, T> sm;
-    const int64_t c = blockIdx.x;
-    if (h.mask[c]) step_cell<F, NH, T, FENCE, NT, false>(a, c, sm);
-    else fluid_cell<F, NH, T>(a, h, c, sm.red);
+    const double dth = a.dt / hc;
+    double U[5];
+    for (int x = 0; x < 5; ++x) U[x] = a.mom[x * n + c] - dth * acc[x];
+    for (int x = 0; x < 5; ++x) a.mom[x * n + c] = U[x];
+    const double k2 = (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0];
+    if (!(U[0] > 0.0) || !(2.0 * U[4] - k2 > 0.0)) *a.flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -673,12 +744,16 @@ hipError_t labels_dispatch(const void *f, float *r, int64_t n, const VelGrid &g,
 
 template <typename F>
 hipError_t hybrid_dispatch(const StepArgs &a, const HybArgs &h, hipStream_t st) {
-    const dim3 grid{unsigned(a.n_cells), 1, 1};
-#define DVM_HYB(NH, T, W, FN)                                                                        \
-    case NH:                                                                                         \
-        hipLaunchKernelGGL((k_hybrid_prep<F, NH, T>), grid, dim3(T), 0, st, a, h);                 \
-        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;                          \
-        hipLaunchKernelGGL((k_step_hybrid<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, a, h);   \
+    const dim3 grid{unsigned(a.n_cells), 1, 1}, g256{unsigned((a.n_cells + 255) / 256), 1, 1};
+    hipLaunchKernelGGL(k_fluid_state, g256, dim3(256), 0, st, a, h);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define DVM_HYB(NH, T, W, FN)                                                                      \
+    case NH:                                                                                       \
+        hipLaunchKernelGGL((k_hybrid_rows<F, NH, T>), grid, dim3(T), 0, st, a, h);               \
+        e = hipGetLastError();                                                                     \
+        if (e != hipSuccess) return e;                                                             \
+        hipLaunchKernelGGL((k_step_hybrid<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, a, h); \
         break;
     switch (a.g.nh) {
         DVM_HYB(2, 64, 4, 0)
@@ -689,6 +764,9 @@ hipError_t hybrid_dispatch(const StepArgs &a, const HybArgs &h, hipStream_t st) 
     default: return hipErrorInvalidValue;
     }
 #undef DVM_HYB
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fluid_update, g256, dim3(256), 0, st, a, h);
     return hipGetLastError();
 }
 

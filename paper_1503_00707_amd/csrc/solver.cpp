@@ -165,7 +165,9 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     if (s->muscl) o += 3 * s->f_bytes;
     s->hybrid = p->hybrid != 0;
     s->off_hyb = o;
-    if (s->hybrid) o += 2 * align256(size_t(s->n)) + align256(size_t(s->n) * kFluxRecord * 8);
+    if (s->hybrid)
+        o += 3 * align256(size_t(s->n)) + align256(size_t(s->n) * kFluxRecord * 8) +
+             align256(size_t(s->n) * kFaceRecord * 8);
     s->ws_bytes = o;
     if (nh == 12) s->sweep_k = 3;
     *out = s;

@@ -35,7 +35,8 @@ struct dvm_solver {
     // workspace sections (byte offsets)
     size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
     size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
-    size_t off_hyb = 0;          // hybrid: effective mask [n], previous mask [n], flux sums [n][66]
+    size_t off_hyb = 0;          // hybrid: masks (effective, previous, row flags) [n], flux sums [n][66],
+                                 // interface face fluxes [n][6][5]
     bool hybrid = false;
     bool hybrid_fluid = false;   // fluid cells may exist (their f is stale)
     bool muscl = false;

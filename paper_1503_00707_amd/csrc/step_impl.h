@@ -483,9 +483,18 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
     }
 }
 
+// A step-cell hook runs after the cell's own values are loaded and before
+// the transport overwrites them (the hybrid step records interface fluxes).
+struct NoHook {
+    template <typename F, int NH, int T>
+    __device__ __forceinline__ void apply(const StepArgs &, const CellView &, int64_t, const Regs<F, NH, T> &,
+                                          double *) const {}
+};
+
 // One fused step of cell c by the calling workgroup.
-template <typename F, int NH, int T, int FENCE, bool NT, bool MU>
-__device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem<F, NH, T> &sm) {
+template <typename F, int NH, int T, int FENCE, bool NT, bool MU, class Hook = NoHook>
+__device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem<F, NH, T> &sm,
+                                          const Hook &hook = Hook()) {
     constexpr int B = NH * NH * NH;
     constexpr int64_t NV = 8 * B;
     using L = Lane<NH, T>;
@@ -531,6 +540,8 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
         }
         __syncthreads();
     }
+
+    hook.template apply<F, NH, T>(a, cell, c, fo, sm.red);
 
     // one row descriptor per face for the main transport pass: the upwind
     // cell's average (first order) or its downwind MUSCL face value

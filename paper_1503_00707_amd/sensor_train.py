@@ -28,8 +28,8 @@ LABEL_THRESHOLD = 0.05
 NV, VMAX = 8, 4.5
 
 
-def c1_mesh():
-    return I.uniform_forest((1, 1, 1), 4, 1.0)
+def c1_mesh(level=4):
+    return I.uniform_forest((1, 1, 1), level, 1.0)
 
 
 def generate(runs, seed0=0, steps=20, keep=256, precision=D.PREC_FP32, log=None):
@@ -58,7 +58,7 @@ def generate(runs, seed0=0, steps=20, keep=256, precision=D.PREC_FP32, log=None)
     return torch.cat(xs), torch.cat(rs)
 
 
-def train(x, r, epochs=4, batch=4096, lr=2e-3, seed=0, log=None):
+def train(x, r, epochs=10, batch=4096, lr=3e-3, seed=0, log=None):
     """a network trained on (x, r > threshold); returns (net, per-epoch mean loss, pos_weight)"""
     import torch
     y = (r > LABEL_THRESHOLD).float()
@@ -72,9 +72,10 @@ def train(x, r, epochs=4, batch=4096, lr=2e-3, seed=0, log=None):
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(n), device="cuda")
         losses = []
+        lr_ep = lr * 0.5 * (1.0 + math.cos(math.pi * ep / epochs))  # cosine decay per epoch
         for b0 in range(0, n - batch + 1, batch):
             sel = perm[b0:b0 + batch]
-            net.train_step(x[sel], y[sel], lr=lr, pos_weight=pos_weight)
+            net.train_step(x[sel], y[sel], lr=lr_ep, pos_weight=pos_weight)
             if (b0 // batch) % 64 == 0:
                 losses.append(net.grads_and_loss()[1])
         hist.append(float(np.mean(losses)))
@@ -103,16 +104,18 @@ def _moment_error(m, ref):
     return float((np.abs(m - ref).max(axis=1) / scale).max())
 
 
-def evaluate(net, kappa=None, fields="sine_rho", field_args=None, tau=0.1, steps=20, precision=D.PREC_FP32):
-    """hybrid (sensor every step) vs full DVM on one flow of the C1 mesh:
-    dict with the moment error, mean kinetic fraction, and both step times"""
+def evaluate(net, kappa=None, fields="sine_rho", field_args=None, tau=0.1, steps=20, precision=D.PREC_FP32,
+             level=4, nv=NV, vmax=VMAX):
+    """hybrid (sensor every step) vs full DVM on one flow of the periodic
+    unit cube at 2^level cells per side (4: the C1 mesh): dict with the moment
+    error, mean kinetic fraction, and both step times"""
     import torch
     field_args = {"a": 0.1} if field_args is None else field_args
-    forest = c1_mesh()
+    forest = c1_mesh(level)
     mesh = D.Mesh(forest)
     t = mesh.tables()
     prim = I.fields(fields, I.leaf_centres(forest)[t["input"]], **field_args)
-    p = D.make_params(NV, VMAX, precision=precision, tau_or_kn=tau, hybrid=True)
+    p = D.make_params(nv, vmax, precision=precision, tau_or_kn=tau, hybrid=True)
     full = D.Solver(mesh, p)
     full.init_maxwellian(prim)
     hyb = D.Solver(mesh, p)

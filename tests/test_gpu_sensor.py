@@ -199,3 +199,18 @@ def test_hybrid_all_fluid_uniform_state_stationary_and_conservative():
     assert rc == 0 and not bad
     scale = np.array([tot0[0]] * 4 + [tot0[4]])
     assert np.all(np.abs(tot - tot0) <= 1e-13 * scale)
+
+
+def test_trained_sensor_hybrid_is_faster_than_full_dvm_within_1e3():
+    """The network trained on GPU-generated DVM labels drives the hybrid on
+    the C1 flow (rho = 1 + 0.1 sin 2 pi x) on 32^3 cells x 24^3 velocities:
+    moment error vs full DVM within 1e-3 after 20 steps, and faster than
+    full DVM (fluid cells cost O(N) per face instead of O(N^3))."""
+    from paper_1503_00707_amd import sensor_train as T
+    x, r = T.generate(200, seed0=0)
+    net, hist, _ = T.train(x, r, epochs=2)
+    assert hist[-1] < hist[0] + 1e-9 and np.isfinite(hist[-1])
+    res = T.evaluate(net, level=5, nv=24, vmax=6.0)
+    print(res)
+    assert res["error"] <= 1e-3
+    assert res["speedup"] > 2.0
