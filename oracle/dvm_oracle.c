@@ -601,12 +601,26 @@ typedef struct {
     const or_mesh *m;
     or_params p;
     or_vgrid g;
-    double *f, *fn;      /* [n_cells][nv] */
+    double *f, *fn;      /* [n_rows][nv] */
     double *ghost_in;    /* corrected inflow Maxwellian */
     double *wall_m1;     /* corrected M(1, 0, T_wall) */
-    double *sigma;       /* MUSCL slopes [n_cells][3][nv] */
+    double *sigma;       /* MUSCL slopes [n_rows][3][nv] */
     int flag;            /* sticky OR_ERR_NONPHYSICAL */
+    /* Held cells.  A full solver holds every cell (row == cell, the arrays
+     * below NULL).  A subset solver holds only the listed cells: f is known
+     * exactly only where every value it depends on was held, and since
+     * eq. (2) couples a cell to its face neighbours only, the exact region
+     * shrinks by one face layer per step (two with MUSCL, whose slopes read
+     * the neighbours' neighbours).  valid[] marks the rows still exact. */
+    int64_t n_rows;
+    int64_t *cells;      /* row -> cell */
+    int64_t *row;        /* cell -> row, -1 when not held */
+    uint8_t *valid, *valid_n, *sig_ok;
 } or_solver;
+
+static int64_t row_of(const or_solver *s, int64_t c) { return s->row ? s->row[c] : c; }
+static int64_t cell_of(const or_solver *s, int64_t r) { return s->cells ? s->cells[r] : r; }
+static const double *f_of(const or_solver *s, int64_t c) { return s->f + row_of(s, c) * s->g.nv; }
 
 static int target_of_prim(const double prim[5], double target[5]) {
     double rho = prim[0], T = prim[4];
@@ -620,18 +634,38 @@ static int target_of_prim(const double prim[5], double target[5]) {
 void or_solver_free(or_solver *s) {
     if (!s) return;
     free(s->f); free(s->fn); free(s->ghost_in); free(s->wall_m1); free(s->sigma);
+    free(s->cells); free(s->row); free(s->valid); free(s->valid_n); free(s->sig_ok);
     vgrid_free(&s->g);
     free(s);
 }
 
-int or_solver_new(const or_mesh *m, const or_params *p, or_solver **out) {
+/* n_sub < 0: every cell; else the n_sub cells listed in ascending order */
+int or_solver_new_subset(const or_mesh *m, const or_params *p, int64_t n_sub, const int64_t *sub, or_solver **out) {
     for (int a = 0; a < 3; ++a)
         if (p->nv[a] < 1 || !(p->vhi[a] > p->vlo[a])) return OR_ERR_ARG;
+    if (n_sub >= 0) {
+        if (n_sub < 1 || !sub) return OR_ERR_ARG;
+        for (int64_t r = 0; r < n_sub; ++r)
+            if (sub[r] < 0 || sub[r] >= m->n_cells || (r && sub[r] <= sub[r - 1])) return OR_ERR_ARG;
+    }
     or_solver *s = (or_solver *)calloc(1, sizeof(or_solver));
     s->m = m;
     s->p = *p;
     vgrid_init(&s->g, p->nv, p->vlo, p->vhi);
-    size_t sz = (size_t)m->n_cells * (size_t)s->g.nv;
+    s->n_rows = n_sub < 0 ? m->n_cells : n_sub;
+    if (n_sub >= 0) {
+        s->cells = (int64_t *)malloc((size_t)n_sub * sizeof(int64_t));
+        memcpy(s->cells, sub, (size_t)n_sub * sizeof(int64_t));
+        s->row = (int64_t *)malloc((size_t)m->n_cells * sizeof(int64_t));
+        for (int64_t c = 0; c < m->n_cells; ++c) s->row[c] = -1;
+        for (int64_t r = 0; r < n_sub; ++r) s->row[sub[r]] = r;
+        s->valid = (uint8_t *)malloc((size_t)n_sub);
+        s->valid_n = (uint8_t *)malloc((size_t)n_sub);
+        s->sig_ok = (uint8_t *)malloc((size_t)n_sub);
+        memset(s->valid, 1, (size_t)n_sub);
+        memset(s->sig_ok, 1, (size_t)n_sub);
+    }
+    size_t sz = (size_t)s->n_rows * (size_t)s->g.nv;
     s->f = (double *)calloc(sz, sizeof(double));
     s->fn = (double *)calloc(sz, sizeof(double));
     s->ghost_in = (double *)calloc((size_t)s->g.nv, sizeof(double));
@@ -660,14 +694,24 @@ int or_solver_new(const or_mesh *m, const or_params *p, or_solver **out) {
     return OR_OK;
 }
 
-int64_t or_solver_nv(const or_solver *s) { return s->g.nv; }
-void or_set_f(or_solver *s, const double *f) { memcpy(s->f, f, (size_t)s->m->n_cells * s->g.nv * sizeof(double)); }
-void or_get_f(const or_solver *s, double *f) { memcpy(f, s->f, (size_t)s->m->n_cells * s->g.nv * sizeof(double)); }
-int or_flag(const or_solver *s) { return s->flag; }
+int or_solver_new(const or_mesh *m, const or_params *p, or_solver **out) {
+    return or_solver_new_subset(m, p, -1, NULL, out);
+}
 
-/* f := corrected Maxwellian of (rho, ux, uy, uz, T) per cell; prim is [5][n_cells] */
+int64_t or_solver_nv(const or_solver *s) { return s->g.nv; }
+int64_t or_solver_rows(const or_solver *s) { return s->n_rows; }
+void or_set_f(or_solver *s, const double *f) { memcpy(s->f, f, (size_t)s->n_rows * s->g.nv * sizeof(double)); }
+void or_get_f(const or_solver *s, double *f) { memcpy(f, s->f, (size_t)s->n_rows * s->g.nv * sizeof(double)); }
+int or_flag(const or_solver *s) { return s->flag; }
+/* 1 per row whose state is exact (always 1 for a full solver) */
+void or_valid(const or_solver *s, uint8_t *out) {
+    if (s->valid) memcpy(out, s->valid, (size_t)s->n_rows);
+    else memset(out, 1, (size_t)s->n_rows);
+}
+
+/* f := corrected Maxwellian of (rho, ux, uy, uz, T) per held cell; prim is [5][n_rows] */
 int or_init_maxwellian(or_solver *s, const double *prim) {
-    int64_t n = s->m->n_cells;
+    int64_t n = s->n_rows;
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : err)
     for (int64_t c = 0; c < n; ++c) {
@@ -698,7 +742,7 @@ static double wall_density(const or_solver *s, int64_t c, int f) {
     const or_vgrid *g = &s->g;
     double num = 0.0, den = 0.0, sg = face_sign(f);
     int axis = f / 2;
-    const double *fc = s->f + c * g->nv;
+    const double *fc = f_of(s, c);
     for (int64_t v = 0; v < g->nv; ++v) {
         double xi[3];
         vgrid_xi(g, v, xi);
@@ -725,22 +769,42 @@ static double neighbour_mean(const or_solver *s, int64_t c, int f, int64_t v, do
     double h = cell_h(m, c);
     int ty = m->type[c * 6 + f];
     const int32_t *nb = &m->nbr[(c * 6 + f) * 4];
-    int64_t nv = s->g.nv;
     switch (ty) {
-    case OR_FACE_SAME: *dist = h; return s->f[nb[0] * nv + v];
-    case OR_FACE_COARSER: *dist = 1.5 * h; return s->f[nb[0] * nv + v];
+    case OR_FACE_SAME: *dist = h; return f_of(s, nb[0])[v];
+    case OR_FACE_COARSER: *dist = 1.5 * h; return f_of(s, nb[0])[v];
     case OR_FACE_FINER:
         *dist = 0.75 * h;
-        return 0.25 * (s->f[nb[0] * nv + v] + s->f[nb[1] * nv + v] + s->f[nb[2] * nv + v] + s->f[nb[3] * nv + v]);
+        return 0.25 * (f_of(s, nb[0])[v] + f_of(s, nb[1])[v] + f_of(s, nb[2])[v] + f_of(s, nb[3])[v]);
     case OR_FACE_INFLOW: *dist = h; return s->ghost_in[v];
-    default: *dist = h; return s->f[c * nv + v]; /* OUTFLOW: zero gradient */
+    default: *dist = h; return f_of(s, c)[v]; /* OUTFLOW: zero gradient */
     }
 }
+
+/* subset solver: 1 when every face neighbour of cell c is held and has
+ * flag ok[] set (domain faces need nothing) */
+static int neighbours_ok(const or_solver *s, int64_t c, const uint8_t *ok) {
+    const or_mesh *m = s->m;
+    for (int f = 0; f < 6; ++f) {
+        int ty = m->type[c * 6 + f];
+        int k = ty == OR_FACE_FINER ? 4 : (ty == OR_FACE_SAME || ty == OR_FACE_COARSER) ? 1 : 0;
+        for (int q = 0; q < k; ++q) {
+            int64_t r = s->row[m->nbr[(c * 6 + f) * 4 + q]];
+            if (r < 0 || !ok[r]) return 0;
+        }
+    }
+    return 1;
+}
+
 static void or_muscl_sigma(or_solver *s) {
     const or_mesh *m = s->m;
-    int64_t nv = s->g.nv, n = m->n_cells;
+    int64_t nv = s->g.nv, n = s->n_rows;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t c = 0; c < n; ++c) {
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t c = cell_of(s, r);
+        if (s->valid) {
+            s->sig_ok[r] = s->valid[r] && neighbours_ok(s, c, s->valid);
+            if (!s->sig_ok[r]) continue;
+        }
         int wall = 0;
         for (int f = 0; f < 6; ++f) wall |= m->type[c * 6 + f] == OR_FACE_WALL;
         for (int axis = 0; axis < 3; ++axis)
@@ -750,20 +814,20 @@ static void or_muscl_sigma(or_solver *s) {
                     double dm, dp;
                     double fm = neighbour_mean(s, c, 2 * axis, v, &dm);
                     double fp = neighbour_mean(s, c, 2 * axis + 1, v, &dp);
-                    double fc = s->f[c * nv + v];
+                    double fc = f_of(s, c)[v];
                     sig = minmod((fc - fm) / dm, (fp - fc) / dp);
                 }
-                s->sigma[(c * 3 + axis) * nv + v] = sig;
+                s->sigma[(r * 3 + axis) * nv + v] = sig;
             }
     }
 }
 
 /* value of cell c's distribution at its face f for velocity v */
 static double face_value(const or_solver *s, int64_t c, int f, int64_t v) {
-    double val = s->f[c * s->g.nv + v];
+    double val = f_of(s, c)[v];
     if (s->p.scheme == 1) {
         double h = cell_h(s->m, c);
-        val += face_sign(f) * 0.5 * h * s->sigma[(c * 3 + f / 2) * s->g.nv + v];
+        val += face_sign(f) * 0.5 * h * s->sigma[(row_of(s, c) * 3 + f / 2) * s->g.nv + v];
     }
     return val;
 }
@@ -781,10 +845,19 @@ static int opposite(int f) { return f ^ 1; }
 static void transport(or_solver *s, double dt) {
     const or_mesh *m = s->m;
     const or_vgrid *g = &s->g;
-    int64_t nv = g->nv, n = m->n_cells;
+    int64_t nv = g->nv, n = s->n_rows;
     if (s->p.scheme == 1) or_muscl_sigma(s);
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t c = 0; c < n; ++c) {
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t c = cell_of(s, r);
+        if (s->valid) { /* subset: exact only if everything read below is exact */
+            const uint8_t *ok = s->p.scheme == 1 ? s->sig_ok : s->valid;
+            s->valid_n[r] = ok[r] && neighbours_ok(s, c, ok);
+            if (!s->valid_n[r]) {
+                memcpy(s->fn + r * nv, s->f + r * nv, (size_t)nv * sizeof(double));
+                continue;
+            }
+        }
         double h = cell_h(m, c), V = h * h * h;
         double rho_w[6] = {0, 0, 0, 0, 0, 0};
         for (int f = 0; f < 6; ++f)
@@ -812,13 +885,14 @@ static void transport(or_solver *s, double dt) {
                     for (int q = 0; q < 4; ++q) acc += (0.5 * h) * (0.5 * h) * xn * face_value(s, nb[q], opposite(f), v);
                     break;
                 case OR_FACE_INFLOW: acc += h * h * xn * s->ghost_in[v]; break;
-                case OR_FACE_OUTFLOW: acc += h * h * xn * s->f[c * nv + v]; break;
+                case OR_FACE_OUTFLOW: acc += h * h * xn * s->f[r * nv + v]; break;
                 case OR_FACE_WALL: acc += h * h * xn * rho_w[f] * s->wall_m1[v]; break;
                 }
             }
-            s->fn[c * nv + v] = s->f[c * nv + v] - dt / V * acc;
+            s->fn[r * nv + v] = s->f[r * nv + v] - dt / V * acc;
         }
     }
+    if (s->valid) { uint8_t *t = s->valid; s->valid = s->valid_n; s->valid_n = t; }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -858,7 +932,7 @@ static int collide_cell(const or_vgrid *g, const or_params *p, double dt, const 
 
 /* one full step: transport, then collision (Lie splitting) */
 int or_step(or_solver *s, double dt, int n_steps) {
-    int64_t n = s->m->n_cells, nv = s->g.nv;
+    int64_t n = s->n_rows, nv = s->g.nv;
     for (int it = 0; it < n_steps; ++it) {
         transport(s, dt);
         int err = 0;
@@ -866,8 +940,13 @@ int or_step(or_solver *s, double dt, int n_steps) {
         {
             double *work = (double *)malloc((size_t)nv * sizeof(double));
 #pragma omp for schedule(dynamic, 16)
-            for (int64_t c = 0; c < n; ++c)
-                if (collide_cell(&s->g, &s->p, dt, s->fn + c * nv, s->f + c * nv, work)) err |= 1;
+            for (int64_t r = 0; r < n; ++r) {
+                if (s->valid && !s->valid[r]) { /* not exact any more: carried, not collided */
+                    memcpy(s->f + r * nv, s->fn + r * nv, (size_t)nv * sizeof(double));
+                    continue;
+                }
+                if (collide_cell(&s->g, &s->p, dt, s->fn + r * nv, s->f + r * nv, work)) err |= 1;
+            }
             free(work);
         }
         if (err) s->flag = OR_ERR_NONPHYSICAL;
@@ -881,26 +960,26 @@ void or_transport(or_solver *s, double dt) {
     double *t = s->f; s->f = s->fn; s->fn = t;
 }
 
-/* moments [5][n_cells]: rho, rho ux, rho uy, rho uz, E of the current f */
+/* moments [5][n_rows]: rho, rho ux, rho uy, rho uz, E of the current f */
 void or_moments(const or_solver *s, double *out) {
-    int64_t n = s->m->n_cells;
+    int64_t n = s->n_rows;
 #pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < n; ++c) {
+    for (int64_t r = 0; r < n; ++r) {
         double mom[5];
-        moments_of(&s->g, s->f + c * s->g.nv, mom);
-        for (int a = 0; a < 5; ++a) out[a * n + c] = mom[a];
+        moments_of(&s->g, s->f + r * s->g.nv, mom);
+        for (int a = 0; a < 5; ++a) out[a * n + r] = mom[a];
     }
 }
 
-/* global conserved quantities sum_c V_c (rho, rho u, E), in cell order */
+/* global conserved quantities sum_c V_c (rho, rho u, E) over the held cells, in cell order */
 void or_global_sums(const or_solver *s, double out[5]) {
-    int64_t n = s->m->n_cells;
+    int64_t n = s->n_rows;
     double *mom = (double *)malloc((size_t)5 * n * sizeof(double));
     or_moments(s, mom);
     for (int a = 0; a < 5; ++a) out[a] = 0.0;
-    for (int64_t c = 0; c < n; ++c) {
-        double h = cell_h(s->m, c), V = h * h * h;
-        for (int a = 0; a < 5; ++a) out[a] += V * mom[a * n + c];
+    for (int64_t r = 0; r < n; ++r) {
+        double h = cell_h(s->m, cell_of(s, r)), V = h * h * h;
+        for (int a = 0; a < 5; ++a) out[a] += V * mom[a * n + r];
     }
     free(mom);
 }

@@ -48,6 +48,10 @@ def lib():
         L.or_mesh_n_leaves.restype = C.c_int64
         L.or_mesh_export.argtypes = [P, u64p, i64p, u8p, i32p, u8p, i32p]
         L.or_solver_new.argtypes = [P, C.POINTER(OrParams), C.POINTER(P)]
+        L.or_solver_new_subset.argtypes = [P, C.POINTER(OrParams), C.c_int64, P, C.POINTER(P)]
+        L.or_solver_rows.argtypes = [P]
+        L.or_solver_rows.restype = C.c_int64
+        L.or_valid.argtypes = [P, u8p]
         L.or_solver_free.argtypes = [P]
         L.or_solver_nv.argtypes = [P]
         L.or_solver_nv.restype = C.c_int64
@@ -132,6 +136,22 @@ class Mesh:
         return dict(key=key, input=inp, level=lev, ijk=ijk.reshape(n, 3), type=ty.reshape(n, 6),
                     nbr=nb.reshape(n, 6, 4))
 
+    def cone(self, cells, hops):
+        """the cells within `hops` face-neighbour steps of `cells` (sorted):
+        what the state of `cells` after `hops` transport steps depends on"""
+        t = self.tables()
+        ty, nb = t["type"], t["nbr"]
+        seen = np.zeros(self.n_cells, bool)
+        front = np.unique(np.asarray(cells, np.int64))
+        seen[front] = True
+        for _ in range(int(hops)):
+            tf = ty[front]
+            k = np.where(tf == FACE_FINER, 4, np.where((tf == FACE_SAME) | (tf == FACE_COARSER), 1, 0))
+            nxt = np.unique(nb[front][np.arange(4)[None, None, :] < k[:, :, None]]).astype(np.int64)
+            front = nxt[~seen[nxt]]
+            seen[front] = True
+        return np.nonzero(seen)[0].astype(np.int64)
+
     def __del__(self):
         if getattr(self, "h", None):
             lib().or_mesh_free(self.h)
@@ -154,16 +174,32 @@ def make_params(nv, vlo, vhi, scheme=0, collision=0, tau_mode=0, tau_or_kn=0.1,
 
 
 class Solver:
-    def __init__(self, mesh: Mesh, params: OrParams):
+    """The oracle's state on every cell of the mesh, or (cells = ascending
+    cell indices) only on those cells: then rows follow `cells`, and valid()
+    tells which rows are still exact (each step loses the cells that read a
+    neighbour not held or no longer exact)."""
+
+    def __init__(self, mesh: Mesh, params: OrParams, cells=None):
         self.mesh = mesh
         self.params = params
         h = C.c_void_p()
-        rc = lib().or_solver_new(mesh.h, C.byref(params), C.byref(h))
+        if cells is None:
+            rc = lib().or_solver_new(mesh.h, C.byref(params), C.byref(h))
+            self.cells = None
+        else:
+            self.cells = np.ascontiguousarray(cells, np.int64)
+            rc = lib().or_solver_new_subset(mesh.h, C.byref(params), self.cells.shape[0],
+                                            self.cells.ctypes.data_as(C.c_void_p), C.byref(h))
         if rc:
             raise RuntimeError(f"or_solver_new: {rc}")
         self.h = h
         self.nv = int(lib().or_solver_nv(h))
-        self.n = mesh.n_cells
+        self.n = int(lib().or_solver_rows(h))
+
+    def valid(self):
+        out = np.zeros(self.n, np.uint8)
+        lib().or_valid(self.h, out)
+        return out.astype(bool)
 
     def set_f(self, f):
         lib().or_set_f(self.h, np.ascontiguousarray(f, np.float64).reshape(-1))

@@ -374,3 +374,50 @@ def test_nonphysical_flag():
     f0[3] = -1.0
     s.set_f(f0)
     assert s.step(0.01, 1) == -5
+
+
+@pytest.mark.parametrize("scheme,bc", [(0, "periodic"), (1, "periodic"), (0, "open_wall"), (1, "open_wall")])
+def test_subset_solver_exact_rows_equal_full_solver(scheme, bc):
+    """Eq. 2 couples a cell only to its face neighbours, so a solver holding
+    just the cells within k face-hops (2k with MUSCL) of a sample reproduces
+    the full solver on that sample after k steps.  Every row the subset
+    solver calls exact must equal the full solver bitwise, the samples must be
+    among them, and one hop less must lose a sample."""
+    nv, lo, hi = (6, 6, 6), (-5.0,) * 3, (5.0,) * 3
+    bcs = (0,) * 6 if bc == "periodic" else (I.INFLOW,) + (I.OUTFLOW,) * 5
+    solid = None
+    if bc == "periodic":
+        f = balanced(I.random_forest(12, (4, 4, 4), 2, 0.2))
+    else:
+        f = balanced(dataclasses.replace(I.sphere_refinement(base=(4, 4, 4), levels=2, radius=0.3), bc=bcs))
+        solid = I.solid_flags(f, (0.5, 0.5, 0.5), 0.3, 2)
+        assert solid.any()
+    kw = dict(scheme=scheme, tau_mode=1, tau_or_kn=0.05, inflow=(1.0, 1.2, 0.0, 0.0, 1.0), solid=solid)
+    m, full = solver_for(f, nv, lo, hi, **kw)
+    t = m.tables()
+    x = (t["ijk"] + 0.5) * (f.h0 / 2.0 ** t["level"])[:, None]
+    prim = np.stack([1 + 0.3 * np.sin(2 * np.pi * x[:, 0]), 0.2 * np.cos(2 * np.pi * x[:, 1]),
+                     0.1 * np.sin(2 * np.pi * x[:, 2]), 0 * x[:, 0], 1 + 0.2 * x[:, 2]])
+    full.init_maxwellian(prim)
+    dt = full.dt_cfl(0.5)
+    k = 2
+    hops = k * (2 if scheme == 1 else 1)
+    rng = np.random.default_rng(5)
+    samples = np.sort(rng.choice(m.n_cells, 4, replace=False))
+    if bc == "open_wall":  # one sample next to the wall
+        samples = np.unique(np.append(samples, np.nonzero((t["type"] == O.FACE_WALL).any(1))[0][0]))
+    assert full.step(dt, k) == 0
+    ref = full.get_f()
+    for r_hops, expect_all in ((hops, True), (hops - 1, False)):
+        cells = m.cone(samples, r_hops)
+        assert cells.shape[0] < m.n_cells
+        sub = O.Solver(m, O.make_params(nv, lo, hi, **{a: b for a, b in kw.items() if a != "solid"}), cells)
+        sub.init_maxwellian(prim[:, cells])
+        assert sub.dt_cfl(0.5) == dt
+        assert sub.step(dt, k) == 0
+        ok = sub.valid()
+        got = sub.get_f()
+        assert not ok.all()
+        assert np.array_equal(got[ok], ref[cells[ok]])
+        at = np.searchsorted(cells, samples)
+        assert ok[at].all() == expect_all
