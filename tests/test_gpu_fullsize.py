@@ -1,0 +1,128 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark times (FP32 f, default kernel shape, fused
+engine, one step + global sums per step), on sampled cells.
+
+The oracle cannot hold 1e6 cells x 24^3 velocities in FP64, but eq. 2
+couples a cell to its face neighbours only: after k steps a cell's state
+depends on the cells within k face-hops (2k with MUSCL, whose slopes read the
+neighbours' neighbours).  The oracle therefore runs on that cone around the
+samples only (its subset solver, pinned bitwise against the full solver on
+small meshes) and the library on the whole mesh; the samples are compared
+cell by cell.  Samples: cells at the density jump, at the periodic wrap, on
+both sides of level jumps, next to the wall and the inflow, and at random.
+"""
+import dataclasses
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+def _moment_scale(mom):
+    """reading of "relative": (max rho, max rho sqrt(max T) for rho u, max E)"""
+    rho = mom[0]
+    u = mom[1:4] / rho
+    T = (2 * mom[4] / rho - (u * u).sum(0)) / 3
+    su = rho.max() * np.sqrt(T.max())
+    return np.array([rho.max(), su, su, su, mom[4].max()])
+
+
+def _pick(rng, pool, k):
+    pool = np.asarray(pool)
+    assert pool.size >= k
+    return rng.choice(pool, k, replace=False)
+
+
+def _samples(name, forest, tables, rng):
+    n = tables["type"].shape[0]
+    cell_input = tables["input"]
+    x = I.leaf_centres(forest)[cell_input]
+    h = forest.h0 / 2.0 ** forest.level[cell_input].astype(np.float64)
+    ty = tables["type"]
+    picks = [_pick(rng, np.nonzero((ty == O.FACE_FINER).any(1))[0], 1),
+             _pick(rng, np.nonzero((ty == O.FACE_COARSER).any(1))[0], 1),
+             rng.choice(n, 8, replace=False)]
+    if name.startswith("octree"):
+        picks.append(_pick(rng, np.nonzero(np.abs(x[:, 0] - 0.5) < h)[0], 2))
+        picks.append(_pick(rng, np.nonzero((x[:, 0] < h) | (x[:, 0] > 1.0 - h))[0], 1))
+    else:
+        picks.append(_pick(rng, np.nonzero((ty == O.FACE_WALL).any(1))[0], 2))
+        picks.append(_pick(rng, np.nonzero((ty == O.FACE_INFLOW).any(1))[0], 1))
+    return np.unique(np.concatenate(picks)).astype(np.int64)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name,steps", [("octree64_v24_p40", 10), ("sphere32_v24_muscl", 8)])
+def test_full_size_fp32_sampled_cells_match_oracle(name, steps):
+    import torch
+    t0 = time.time()
+    w = I.workload(name)
+    lev, ijk = O.balance(w.forest)
+    forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
+    solid = None
+    if w.solid_ball is not None:
+        cx, cy, cz, r, lv = w.solid_ball
+        solid = I.solid_flags(forest, (cx, cy, cz), r, lv)
+    nv = w.nv
+    # --- oracle: the cone of the samples only -----------------------------
+    om = O.Mesh(forest, solid)
+    ot = om.tables()
+    rng = np.random.default_rng(2024)
+    samples = _samples(name, forest, ot, rng)
+    hops = steps * (2 if w.scheme == I.SCHEME_MUSCL else 1)
+    cells = om.cone(samples, hops)
+    _log(f"{name}: {om.n_cells} cells, {samples.size} samples, cone of {hops} hops = {cells.size} cells "
+         f"({time.time() - t0:.1f}s)")
+    op = O.make_params(nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
+                       tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall)
+    osub = O.Solver(om, op, cells)
+    prim_all = I.fields(w.fields, I.leaf_centres(forest)[ot["input"]], **w.field_args)
+    osub.init_maxwellian(prim_all[:, cells])
+    dt = osub.dt_cfl(w.cfl)
+    assert osub.step(dt, steps) == 0
+    ok = osub.valid()
+    at = np.searchsorted(cells, samples)
+    assert ok[at].all()
+    mo = osub.moments()
+    scale = _moment_scale(mo[:, ok])
+    fo = osub.get_f()[at]
+    mo = mo[:, at]
+    del osub
+    _log(f"oracle done ({time.time() - t0:.1f}s)")
+    # --- the library on the whole mesh, as the benchmark launches it ------
+    mesh = D.Mesh(forest, solid)
+    dtab = mesh.tables()
+    assert np.array_equal(dtab["input"], ot["input"])
+    p = D.make_params(nv[0], w.vhi[0], precision=D.PREC_FP32, scheme=w.scheme, collision=w.collision,
+                      tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall)
+    s = D.Solver(mesh, p)
+    s.init_maxwellian(prim_all)
+    del prim_all
+    assert s.dt(w.cfl) == pytest.approx(dt, rel=1e-14)
+    for _ in range(steps):
+        s.step(1, dt=dt)
+        s.global_sums()
+    rc, _, bad, done = s.check()
+    assert rc == 0 and not bad and done == steps
+    idx = torch.as_tensor(samples, device="cuda")
+    mg = s.moments()[:, idx].cpu().numpy()
+    fg = s.f_canonical()[idx].double().cpu().numpy()
+    torch.cuda.synchronize()
+    del s
+    torch.cuda.empty_cache()
+    em = (np.abs(mg - mo).max(axis=1) / scale).max()
+    ef = (np.abs(fg - fo).max(axis=1) / np.abs(fo).max(axis=1)).max()
+    _log(f"{name}: moment error {em:.3e}, f error {ef:.3e} over {samples.size} cells "
+         f"({time.time() - t0:.1f}s)")
+    assert em <= 2e-5
+    assert ef <= 1e-5
