@@ -34,6 +34,8 @@ struct StepArgs {
     double tau_or_kn;
     int xcd_log2;            // runs of 2^xcd_log2 consecutive cells kept on one XCD
     const void *face;        // MUSCL face values [3][n_cells][NV] (NULL: first order)
+    const uint32_t *sel;     // the cells this launch steps, one per workgroup (NULL: 0 .. n_cells-1)
+    int64_t n_sel;           // their number (used when sel is set)
 };
 
 struct InitArgs {
@@ -52,6 +54,7 @@ struct StepConfig {
     int xcd_group;   // consecutive cells kept on one XCD
     int nt_store;    // non-temporal stores of the new state
     int wpe;         // waves-per-EU variant (0: the first listed for this shape)
+    int regular;     // 1: the launch holds only cells without FINER or WALL faces (reduced kernel)
 };
 
 // All return hipError_t of the launch (hipErrorInvalidValue: no kernel for N).
@@ -65,6 +68,8 @@ hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n
 hipError_t launch_to_canonical(bool fp64, bool to_canon, const void *src, void *dst, int64_t n, int nh,
                                hipStream_t st);
 bool have_kernel(int nh, int threads, int wpe);
+// a reduced kernel (cells without FINER or WALL faces) exists for this shape
+bool have_regular_kernel(int nh, int threads, int wpe);
 int list_kernels(int nh, int *threads, int *wpe, int cap);
 int default_threads(bool fp64, int nh);
 

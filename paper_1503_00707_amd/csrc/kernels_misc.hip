@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_canon(const F *src, F *dst, int nh, int
 }  // namespace
 
 bool have_kernel(int nh, int threads, int wpe) { return impl::step_config_exists(nh, threads, wpe); }
+bool have_regular_kernel(int nh, int threads, int wpe) { return impl::reg_config_exists(nh, threads, wpe); }
 int list_kernels(int nh, int *threads, int *wpe, int cap) { return impl::step_config_list(nh, threads, wpe, cap); }
 
 int default_threads(bool fp64, int nh) {

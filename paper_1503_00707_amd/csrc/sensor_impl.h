@@ -683,7 +683,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     const int64_t c = blockIdx.x;
     if (!h.mask[c]) return;  // fluid cells: k_fluid_update
     const HybHook hook{h};
-    step_cell<F, NH, T, FENCE, NT, false, HybHook>(a, c, sm, hook);
+    step_cell<F, NH, T, FENCE, NT, false, false, HybHook>(a, c, sm, hook);
 }
 
 // Fluid cells, one thread each: U' = U - dt/h sum_faces (H_out + H_in).

@@ -65,6 +65,15 @@ static hipError_t ensure_lazy(dvm_solver *s, hipStream_t st) {
 }
 
 // Apply a pending relaxation in place so that the buffer holds f itself.
+namespace {
+// two launches (reduced kernel over the regular cells, full kernel over the
+// rest) instead of one: fused engine, first order, kernels compiled
+bool use_split(const dvm_solver *s) {
+    return s->split && !s->muscl && s->n_reg > 0 && have_regular_kernel(s->nh, s->cfg.threads, s->cfg.wpe) &&
+           have_kernel(s->nh, s->cfg_irr.threads, s->cfg_irr.wpe);
+}
+}  // namespace
+
 StepArgs dvm::solver_step_args(const dvm_solver *s, double dt) {
     StepArgs a{};
     a.mom = s->mom;
@@ -140,7 +149,7 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     if (nh == 12 && !fp64) {
         s->cfg.threads = 192;
         s->cfg.wpe = 31;
-        s->cfg.xcd_group = 8;
+        s->cfg.xcd_group = 512;
         s->cfg.nt_store = 1;
     }
     s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
@@ -168,6 +177,18 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     if (s->hybrid)
         o += 3 * align256(size_t(s->n)) + align256(size_t(s->n) * kFluxRecord * 8) +
              align256(size_t(s->n) * kFaceRecord * 8);
+    // selection list: regular cells (no FINER or WALL face) first, then the rest
+    s->off_sel = o;  o += align256(size_t(s->n) * 4);
+    s->sel_host.reserve(size_t(s->n));
+    for (int pass = 0; pass < 2; ++pass)
+        for (int64_t c = 0; c < s->n; ++c) {
+            const DevCell &d = m->table[size_t(c)];
+            bool irregular = false;
+            for (int f = 0; f < 6; ++f) irregular |= d.type[f] == DVM_FACE_FINER || d.type[f] == DVM_FACE_WALL;
+            if (irregular == (pass == 1)) s->sel_host.push_back(uint32_t(c));
+            if (pass == 0 && !irregular) ++s->n_reg;
+        }
+    s->cfg_irr = s->cfg;
     s->ws_bytes = o;
     if (nh == 12) s->sweep_k = 3;
     *out = s;
@@ -215,6 +236,8 @@ int dvm_upload(dvm_solver *s, void *stream) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
     e = hipMemsetAsync(s->ws, 0, s->ws_bytes, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(ws)");
+    e = hipMemcpyAsync(s->ws + s->off_sel, s->sel_host.data(), s->sel_host.size() * 4, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(selection)");
     InitArgs a{};
     a.prim = nullptr;
     a.n = 1;
@@ -319,7 +342,26 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
                 e = launch_face(s->fp64, a, st);
                 if (e != hipSuccess) return hip_fail(e, "MUSCL face values");
             }
-            e = launch_step(s->fp64, a, s->cfg, st);
+            if (use_split(s)) {
+                StepArgs ar = a;
+                ar.sel = s->sel();
+                ar.n_sel = s->n_reg;
+                StepConfig cr = s->cfg;
+                cr.regular = 1;
+                e = s->n_reg > 0 ? launch_step(s->fp64, ar, cr, st) : hipSuccess;
+                if (e == hipSuccess && s->n > s->n_reg) {
+                    StepArgs ai = a;
+                    ai.sel = s->sel() + s->n_reg;
+                    ai.n_sel = s->n - s->n_reg;
+                    StepConfig ci = s->cfg;  // stores and grouping as chosen; its own shape
+                    ci.threads = s->cfg_irr.threads;
+                    ci.wpe = s->cfg_irr.wpe;
+                    ci.regular = 0;
+                    e = launch_step(s->fp64, ai, ci, st);
+                }
+            } else {
+                e = launch_step(s->fp64, a, s->cfg, st);
+            }
             if (e != hipSuccess) return hip_fail(e, "step");
             s->lazy_valid = false;
         }
@@ -461,6 +503,22 @@ int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *x
     *wpe = s->engine == 1 ? k : s->cfg.wpe;
     *xcd_group = s->cfg.xcd_group;
     *nt_store = s->engine == 1 ? s->unit_nt : s->cfg.nt_store;
+    return DVM_OK;
+}
+
+int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t wpe_irr, int32_t *previous) {
+    clear_error();
+    if (!s) return fail(DVM_ERR_ARG, "null solver");
+    if (previous) *previous = s->split ? 1 : 0;
+    if (enable < 0) return DVM_OK;
+    if (threads_irr > 0) {
+        if (!have_kernel(s->nh, threads_irr, wpe_irr))
+            return fail(DVM_ERR_UNSUPPORTED, "no step kernel with %d threads, wpe %d for N = %d", threads_irr, wpe_irr,
+                        2 * s->nh);
+        s->cfg_irr.threads = threads_irr;
+        s->cfg_irr.wpe = wpe_irr;
+    }
+    s->split = enable != 0;
     return DVM_OK;
 }
 

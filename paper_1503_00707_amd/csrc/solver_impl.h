@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -55,6 +57,13 @@ struct dvm_solver {
     size_t off_tab = 0, off_lpart = 0, off_null = 0;
     bool lazy_valid = false;     // records describe f[cur] read as f*
     bool relax_pending = false;  // some record is not the identity
+    // fused engine, first order: cells without FINER or WALL faces ("regular")
+    // step in a reduced kernel, the others in a second launch of the full one
+    bool split = true;
+    int64_t n_reg = 0;             // regular cells: the first n_reg entries of the selection list
+    size_t off_sel = 0;            // selection list [n] (regular cells, then the others; Morton order)
+    std::vector<uint32_t> sel_host;
+    dvm::StepConfig cfg_irr{};     // shape of the launch over the other cells
 
     void *tab() const { return ws + off_tab; }
     void *null_rec() const { return ws + off_null; }  // record n of the table section
@@ -66,6 +75,7 @@ struct dvm_solver {
     int *flag() const { return reinterpret_cast<int *>(ws + off_flag); }
     double *partials() const { return reinterpret_cast<double *>(ws + off_part); }
     double *sums() const { return reinterpret_cast<double *>(ws + off_sums); }
+    const uint32_t *sel() const { return reinterpret_cast<const uint32_t *>(ws + off_sel); }
 };
 
 

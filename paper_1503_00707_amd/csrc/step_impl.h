@@ -32,6 +32,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -195,6 +196,20 @@ struct Lane {
             ax = t / (NH * NH) + q * (T / (NH * NH));
         } else {
             slot_axes<NH>(slot(q), ax, ay, az);
+        }
+    }
+    // the same decode from a copy of the thread index the optimizer cannot
+    // see through: used late in a step, so that the early decode is not kept
+    // alive (in registers or spilled) across the whole step
+    __device__ __forceinline__ void axes_late(int q, int &ax, int &ay, int &az) const {
+        int t = int(threadIdx.x);
+        asm volatile("" : "+v"(t));
+        if (kQInv) {
+            az = t % NH;
+            ay = (t / NH) % NH;
+            ax = t / (NH * NH) + q * (T / (NH * NH));
+        } else {
+            slot_axes<NH>(t + q * T, ax, ay, az);
         }
     }
     template <typename F>
@@ -377,6 +392,9 @@ struct StepSmem {
     double red[NW * 5];
     double rho_w[6];
     MaxwellSmem<F, NH> mx;
+    // FP32: landing area of the FINER / WALL correction loads (per wave: 4
+    // rows x S rounds x 64 lanes), filled by loads that write LDS directly
+    float stage[std::is_same<F, float>::value ? NW : 1][std::is_same<F, float>::value ? 4 * Lane<NH, T>::S : 1][64];
 };
 
 // Transport of the thread's slots; fo holds f on entry and f* on return.
@@ -386,10 +404,10 @@ struct StepSmem {
 // WALL faces are given an empty descriptor there (reads return 0); the
 // correction pass then adds nu * f_up for them, f_up the mean of the four
 // finer rows or rho_w times the wall Maxwellian.
-template <typename F, int NH, int T, bool OCT_FENCE, bool MU>
+template <typename F, int NH, int T, bool OCT_FENCE, bool MU, bool REG>
 __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &cell, const Rsrc (&R1)[6],
                                           const Rsrc (&RD)[3], const F *fin, const F *face, const StepArgs &a,
-                                          const double *rho_w, double dth, double (&m)[5]) {
+                                          const double *rho_w, double dth, double (&m)[5], float *stage) {
     using L = Lane<NH, T>;
     constexpr int S = L::S;
     constexpr int64_t NV = 8 * L::B;
@@ -430,9 +448,10 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
         if (OCT_FENCE) asm volatile("" ::: "memory");
     }
     // correction for FINER and WALL faces: a runtime loop over the faces (one
-    // face's loads in flight at a time), workgroup-uniform branches
+    // face's loads in flight at a time), workgroup-uniform branches; absent
+    // from the reduced kernel, whose cells have no such faces
 #pragma nounroll
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < (REG ? 0 : 6); ++f) {
         const int ty = cell.type_rt(f);
         if (ty != DVM_FACE_FINER && ty != DVM_FACE_WALL) continue;
         const int b = f >> 1, enter = (f & 1) ? 0 : 1;  // sign bit of the velocities entering through f
@@ -450,6 +469,36 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
             r[0] = r[1] = r[2] = r[3] = rsrc(a.wall_m1, kRow);
             sc = F(rho_w[f]);
         }
+        if constexpr (std::is_same<F, float>::value) {
+            // every load of an octant in flight at once, landing in this
+            // wave's part of LDS (no registers held): lane l of a load writes
+            // word l of its 64-word slot
+            float *wst = stage + (threadIdx.x >> 6) * (4 * S * 64);
+            const int lane = threadIdx.x & 63;
+            const int nk = finer ? 4 : 1;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                if (((o >> (2 - b)) & 1) != enter) continue;
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (k < nk)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                r[k], (__attribute__((address_space(3))) void *)(wst + (q * 4 + k) * 64), 4, voff,
+                                L::template soff<F>(o, q), 0, 0);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const float *v = wst + q * 4 * 64 + lane;
+                    const F up = finer ? (v[0] + v[64]) + (v[128] + v[192]) : v[0];
+                    const F nub = b == 0 ? nu[0][q] : b == 1 ? nu[1][q] : nu[2][q];
+                    fo[o][q] += nub * (sc * up);
+                }
+                // the slots are read before the next octant's loads overwrite them
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+        } else {
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
@@ -464,12 +513,13 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
             }
             asm volatile("" ::: "memory");
         }
+        }
     }
 #pragma unroll
     for (int q = 0; q < S; ++q) {
         if (!ln.ok(q)) continue;
         int a3[3];
-        ln.axes(q, a3[0], a3[1], a3[2]);
+        ln.axes_late(q, a3[0], a3[1], a3[2]);
         const double xa = (a3[0] + 0.5) * a.g.dv[0];
         const double ya = (a3[1] + 0.5) * a.g.dv[1];
         const double za = (a3[2] + 0.5) * a.g.dv[2];
@@ -492,7 +542,7 @@ struct NoHook {
 };
 
 // One fused step of cell c by the calling workgroup.
-template <typename F, int NH, int T, int FENCE, bool NT, bool MU, class Hook = NoHook>
+template <typename F, int NH, int T, int FENCE, bool NT, bool MU, bool REG = false, class Hook = NoHook>
 __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem<F, NH, T> &sm,
                                           const Hook &hook = Hook()) {
     constexpr int B = NH * NH * NH;
@@ -517,7 +567,7 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
         for (int o = 0; o < 8; ++o) fo[o][q] = bld<F>(own, voff, L::template soff<F>(o, q));
 
     // diffuse walls: density of the re-emitted Maxwellian (zero net mass flux)
-    if (cell.flags() & 1) {
+    if (!REG && (cell.flags() & 1)) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             if (cell.type(f) != DVM_FACE_WALL) continue;
@@ -529,11 +579,15 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
                 int a3[3];
                 ln.axes(q, a3[0], a3[1], a3[2]);
                 const double xa = (a3[axis] + 0.5) * a.g.dv[axis];
+                // the four octants leaving through this face share |xi_axis|:
+                // summed in the storage precision, then widened once
+                F s4 = F(0);
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
                     const int sb = axis == 0 ? (o >> 2) : axis == 1 ? ((o >> 1) & 1) : (o & 1);
-                    if (sb == side) v[0] += xa * double(fo[o][q]);  // leaving through this face
+                    if (sb == side) s4 += fo[o][q];
                 }
+                v[0] += xa * double(s4);
             }
             block_sum<T, 1>(v, sm.red);
             if (tid == 0) sm.rho_w[f] = v[0] / a.wall_den[f];
@@ -567,7 +621,7 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     for (int b = 0; b < 3; ++b) RD[b] = rsrc(MU ? face + (b * a.n_cells + c) * NV : fin, MU ? kRow : 0u);
 
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    transport<F, NH, T, (FENCE != 0), MU>(fo, cell, R1, RD, fin, face, a, sm.rho_w, dth, m);
+    transport<F, NH, T, (FENCE != 0), MU, REG>(fo, cell, R1, RD, fin, face, a, sm.rho_w, dth, m, &sm.stage[0][0][0]);
     block_sum<T, 5>(m, sm.red);
 
     const double w = a.g.w;
@@ -608,12 +662,14 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     relax_store<F, NH, T, NT>(sm.mx, fo, F(e), out);
 }
 
-// One fused step, one cell per workgroup.
-template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false>
+// One fused step, one cell per workgroup: every cell, or the cells listed in
+// a.sel (REG: a list of cells without FINER or WALL faces).
+template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false, bool REG = false>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
     __shared__ StepSmem<F, NH, T> sm;
-    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
-    step_cell<F, NH, T, FENCE, NT, MU>(a, c, sm);
+    const uint32_t b = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
+    const int64_t c = a.sel ? int64_t(as_const_space(a.sel)[b]) : int64_t(b);
+    step_cell<F, NH, T, FENCE, NT, MU, REG>(a, c, sm);
 }
 
 // Batched step: the cells of many independent instances with the same
@@ -811,6 +867,14 @@ __global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelG
     X(12, 576, 5, 1)        \
     X(12, 576, 7, 1)
 
+// reduced kernels (cells without FINER or WALL faces): one shape per N
+#define DVM_REG_CONFIGS(X) \
+    X(2, 64, 4, 0)         \
+    X(4, 64, 5, 0)         \
+    X(6, 256, 6, 0)        \
+    X(8, 256, 5, 0)        \
+    X(12, 192, 3, 1)
+
 // MUSCL step kernels: one shape per N
 #define DVM_MUSCL_CONFIGS(X) \
     X(2, 64, 4, 0)           \
@@ -821,7 +885,19 @@ __global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelG
 
 template <typename F>
 hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t st) {
-    const dim3 grid(unsigned(a.n_cells));
+    const dim3 grid(unsigned(a.sel ? a.n_sel : a.n_cells));
+    if (cfg.regular) {
+        if (!a.sel || a.face) return hipErrorInvalidValue;
+#define X(NH, T, W, FN)                                                                                     \
+        if (a.g.nh == NH && cfg.threads == T && (cfg.wpe == 0 || cfg.wpe == 10 * W + FN)) {                 \
+            if (cfg.nt_store) hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true, false, true>), grid, dim3(T), 0, st, a); \
+            else hipLaunchKernelGGL((k_step<F, NH, T, W, FN, false, false, true>), grid, dim3(T), 0, st, a); \
+            return hipGetLastError();                                                                       \
+        }
+        DVM_REG_CONFIGS(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
     if (a.face) {
 #define X(NH, T, W, FN)                                                                        \
         if (a.g.nh == NH) {                                                                    \
@@ -875,6 +951,14 @@ inline int step_config_list(int nh, int *threads, int *wpe, int cap) {
     DVM_STEP_CONFIGS(X)
 #undef X
     return n;
+}
+
+inline bool reg_config_exists(int nh, int threads, int wpe) {
+#define X(NH, T, W, FN) \
+    if (nh == NH && threads == T && (wpe == 0 || wpe == 10 * W + FN)) return true;
+    DVM_REG_CONFIGS(X)
+#undef X
+    return false;
 }
 
 inline bool step_config_exists(int nh, int threads, int wpe) {

@@ -26,7 +26,7 @@ EXPORTED = [
     "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
     "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
     "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
-    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine",
+    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine", "dvm_tune_split",
     "dvm_batch_create", "dvm_batch_workspace_bytes", "dvm_batch_bind", "dvm_batch_step", "dvm_batch_tune",
     "dvm_batch_info", "dvm_destroy_batch",
     "dvm_features", "dvm_labels", "dvm_mlp_create", "dvm_mlp_workspace_bytes", "dvm_mlp_bind",
@@ -102,6 +102,7 @@ def lib():
         L.dvm_tune_set.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dvm_tune_get.argtypes = [P, P, P, P, P]
         L.dvm_tune_engine.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
+        L.dvm_tune_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_destroy_solver.argtypes = [P]
         L.dvm_destroy_solver.restype = None
         L.dvm_batch_create.argtypes = [P, C.c_int32, C.c_double, C.POINTER(P)]
@@ -309,6 +310,14 @@ class Solver:
         prev = C.c_int32(0)
         _check(lib().dvm_tune_engine(self.h, int(engine), C.byref(prev)), "dvm_tune_engine")
         return int(prev.value)
+
+    def split(self, enable=-1, threads_irr=0, wpe_irr=0):
+        """cells without FINER or WALL faces in a reduced kernel (1) or every
+        cell in one launch (0); <0 only queries; returns the previous setting"""
+        prev = C.c_int32(0)
+        _check(lib().dvm_tune_split(self.h, int(enable), int(threads_irr), int(wpe_irr), C.byref(prev)),
+               "dvm_tune_split")
+        return prev.value
 
     def features(self):
         """[n, 10] float32 sensor features of the current moments"""
