@@ -142,7 +142,8 @@ def gpu_bench(args):
     split = s.split() == 1 and w.scheme == I.SCHEME_UPWIND1
     kernel = ("k_step fused step (transport+moments+Maxwellian+BGK) as two launches: the reduced kernel over "
               "cells without FINER/WALL faces, the full kernel over the rest; events bracket both"
-              if split else "k_step (fused transport+moments+Maxwellian+BGK)")
+              if split else "k_step (fused transport+moments+Maxwellian+BGK, one launch; cells without FINER/WALL "
+              "faces take the reduced code path)")
     return dict(cvu=cvu, total_ms=total_ms, k_ms=k_ms, achieved=achieved, alg_bytes=alg_bytes, n=s.n, nv=s.nv,
                 rc=rc, drift=drift, g0=g0, w=w, fbytes=fbytes, dt=dt, kernel=kernel)
 

@@ -266,9 +266,10 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
  * dvm_tune_split -- fused engine, first order: step the cells that have no
  * FINER or WALL face (a level jump seen from the coarse side, or a wall) in a
  * reduced kernel and the others in a second launch of the full kernel
- * (enable = 1, the default), or every cell in one launch of the full kernel
- * (enable = 0).  Both compute the same step, bitwise: the reduced kernel only
- * leaves out the passes that such cells skip anyway.  threads_irr > 0 also
+ * (enable = 1), or every cell in one launch (enable = 0, the default; each
+ * workgroup takes the reduced code path when its cell allows it).  Both
+ * compute the same step, bitwise: the reduced code only leaves out the passes
+ * that such cells skip anyway.  threads_irr > 0 also
  * chooses the shape (threads per workgroup, waves-per-EU variant as listed by
  * dvm_tune_shapes) of the second launch; DVM_ERR_UNSUPPORTED if it does not
  * exist.  enable < 0 only queries; *previous (may be NULL) receives the

@@ -57,9 +57,11 @@ struct dvm_solver {
     size_t off_tab = 0, off_lpart = 0, off_null = 0;
     bool lazy_valid = false;     // records describe f[cur] read as f*
     bool relax_pending = false;  // some record is not the identity
-    // fused engine, first order: cells without FINER or WALL faces ("regular")
-    // step in a reduced kernel, the others in a second launch of the full one
-    bool split = true;
+    // fused engine, first order: optionally step the cells without FINER or
+    // WALL faces ("regular") in a reduced kernel and the others in a second
+    // launch (off by default: one launch takes the reduced code path per cell
+    // and keeps Morton locality between the two kinds)
+    bool split = false;
     int64_t n_reg = 0;             // regular cells: the first n_reg entries of the selection list
     size_t off_sel = 0;            // selection list [n] (regular cells, then the others; Morton order)
     std::vector<uint32_t> sel_host;

@@ -662,6 +662,19 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     relax_store<F, NH, T, NT>(sm.mx, fo, F(e), out);
 }
 
+// The cell has a FINER or a WALL face (it needs the correction pass).
+__device__ __forceinline__ bool needs_correction(const DevCell *cells, int64_t c) {
+    cuint32_t *rec = as_const_space(reinterpret_cast<const uint32_t *>(cells + c));
+    const uint32_t k0 = rec[24], k1 = rec[25];
+    bool r = false;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const uint32_t ty = ((f < 4 ? k0 : k1) >> (8 * (f & 3))) & 0xffu;
+        r |= ty == DVM_FACE_FINER || ty == DVM_FACE_WALL;
+    }
+    return r;
+}
+
 // One fused step, one cell per workgroup: every cell, or the cells listed in
 // a.sel (REG: a list of cells without FINER or WALL faces).
 template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false, bool REG = false>
@@ -669,7 +682,14 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     __shared__ StepSmem<F, NH, T> sm;
     const uint32_t b = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const int64_t c = a.sel ? int64_t(as_const_space(a.sel)[b]) : int64_t(b);
-    step_cell<F, NH, T, FENCE, NT, MU, REG>(a, c, sm);
+    if constexpr (!MU && !REG) {
+        // every cell in one launch: the reduced code for the cells without
+        // FINER or WALL faces, the full code for the others (uniform branch)
+        if (needs_correction(a.cells, c)) step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
+        else step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
+    } else {
+        step_cell<F, NH, T, FENCE, NT, MU, REG>(a, c, sm);
+    }
 }
 
 // Batched step: the cells of many independent instances with the same
@@ -696,7 +716,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     if (threadIdx.x < sizeof(StepArgs) / 4)
         reinterpret_cast<uint32_t *>(&a)[threadIdx.x] = reinterpret_cast<const uint32_t *>(inst + lo)[threadIdx.x];
     __syncthreads();
-    step_cell<F, NH, T, FENCE, NT, false>(a, int64_t(b - start), sm);
+    const int64_t c = int64_t(b - start);
+    if (needs_correction(a.cells, c)) step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
+    else step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
 }
 
 // MUSCL-minmod face values of the state a.f_in, three planes [3][n][NV] at

@@ -181,17 +181,17 @@ def test_batch_create_errors_host_only():
 
 
 def test_split_setting_host_only():
-    """the regular/irregular split is on by default, can be queried and turned
-    off, and rejects a shape that was not compiled; no device call"""
+    """the regular/irregular split is off by default, can be queried and turned
+    on, and rejects a shape that was not compiled; no device call"""
     import ctypes as C
     m = D.Mesh(I.uniform_forest((1, 1, 1), 2))
     h = C.c_void_p()
     p = D.make_params(24, 6.0)
     assert D.lib().dvm_create_solver(m.h, C.byref(p), C.byref(h)) == D.OK
     prev = C.c_int32(-7)
-    assert D.lib().dvm_tune_split(h, -1, 0, 0, C.byref(prev)) == D.OK and prev.value == 1
-    assert D.lib().dvm_tune_split(h, 0, 0, 0, C.byref(prev)) == D.OK and prev.value == 1
     assert D.lib().dvm_tune_split(h, -1, 0, 0, C.byref(prev)) == D.OK and prev.value == 0
+    assert D.lib().dvm_tune_split(h, 1, 0, 0, C.byref(prev)) == D.OK and prev.value == 0
+    assert D.lib().dvm_tune_split(h, -1, 0, 0, C.byref(prev)) == D.OK and prev.value == 1
     assert D.lib().dvm_tune_split(h, 1, 100, 31, None) == D.ERR_UNSUPPORTED
     assert D.lib().dvm_tune_split(h, 1, 576, 71, None) == D.OK
     D.lib().dvm_destroy_solver(h)
