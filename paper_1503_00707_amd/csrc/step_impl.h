@@ -404,10 +404,11 @@ struct StepSmem {
 // WALL faces are given an empty descriptor there (reads return 0); the
 // correction pass then adds nu * f_up for them, f_up the mean of the four
 // finer rows or rho_w times the wall Maxwellian.
-template <typename F, int NH, int T, bool OCT_FENCE, bool MU, bool REG>
+template <typename F, int NH, int T, bool OCT_FENCE, bool MU, bool REG, bool LATE_OWN>
 __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &cell, const Rsrc (&R1)[6],
-                                          const Rsrc (&RD)[3], const F *fin, const F *face, const StepArgs &a,
-                                          const double *rho_w, double dth, double (&m)[5], float *stage) {
+                                          const Rsrc (&RD)[3], const Rsrc &own, const F *fin, const F *face,
+                                          const StepArgs &a, const double *rho_w, double dth, double (&m)[5],
+                                          float *stage) {
     using L = Lane<NH, T>;
     constexpr int S = L::S;
     constexpr int64_t NV = 8 * L::B;
@@ -429,6 +430,7 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const uint32_t so = L::template soff<F>(o, q);
+            if constexpr (LATE_OWN) fo[o][q] = bld<F>(own, voff, so);
             const F v = fo[o][q];
             const F ux = bld<F>(R1[fx], voff, so);
             const F uy = bld<F>(R1[fy], voff, so);
@@ -558,13 +560,22 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     const Rsrc own = rsrc(fin + c * NV, kRow);
     const double dth = a.dt / (a.h0 / double(1 << cell.level()));
 
-    // own values of every slot and octant, kept in registers for the step
+    // own values of every slot and octant, kept in registers for the step.
+    // Reduced path: loaded octant by octant inside the transport pass, with
+    // the upwind neighbours' values of the same octant, so that a cell's block
+    // is read by the cell and by its concurrently running neighbours at about
+    // the same time (it is still in L2 when they ask for it).  Full path:
+    // loaded here (the wall densities and the step hook need every value
+    // before the transport).
+    constexpr bool kLateOwn = REG && std::is_same<Hook, NoHook>::value;
     F fo[8][S];
     const uint32_t voff = tid * sizeof(F);
+    if constexpr (!kLateOwn) {
 #pragma unroll
-    for (int q = 0; q < S; ++q)
+        for (int q = 0; q < S; ++q)
 #pragma unroll
-        for (int o = 0; o < 8; ++o) fo[o][q] = bld<F>(own, voff, L::template soff<F>(o, q));
+            for (int o = 0; o < 8; ++o) fo[o][q] = bld<F>(own, voff, L::template soff<F>(o, q));
+    }
 
     // diffuse walls: density of the re-emitted Maxwellian (zero net mass flux)
     if (!REG && (cell.flags() & 1)) {
@@ -621,7 +632,8 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     for (int b = 0; b < 3; ++b) RD[b] = rsrc(MU ? face + (b * a.n_cells + c) * NV : fin, MU ? kRow : 0u);
 
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    transport<F, NH, T, (FENCE != 0), MU, REG>(fo, cell, R1, RD, fin, face, a, sm.rho_w, dth, m, &sm.stage[0][0][0]);
+    transport<F, NH, T, (FENCE != 0), MU, REG, kLateOwn>(fo, cell, R1, RD, own, fin, face, a, sm.rho_w, dth, m,
+                                                        &sm.stage[0][0][0]);
     block_sum<T, 5>(m, sm.red);
 
     const double w = a.g.w;
