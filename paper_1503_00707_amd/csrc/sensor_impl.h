@@ -633,12 +633,54 @@ __device__ __forceinline__ void sep_flux(const double *R, int b, int hs, double 
 // the transport overwrites f.
 struct HybHook {
     HybArgs h;
+    // moments of the values leaving through face FACE (its axis and side
+    // compile-time constants, so the octants it selects are static)
+    template <int FACE, typename F, int NH, int T>
+    __device__ __forceinline__ void face_flux(const StepArgs &a, int64_t c, const Regs<F, NH, T> &fo,
+                                              double *red) const {
+        using L = Lane<NH, T>;
+        constexpr int S = L::S;
+        constexpr int b = FACE >> 1, side = FACE & 1;
+        const L ln;
+        // For a round the four leaving octants share |xi| and the sign along
+        // b; only the signs along the other two axes (p, r) change.  So the
+        // five moments need three sums of the stored values, formed in the
+        // storage precision and widened once: S (all four), Sp and Sr (signed
+        // by the sign along p and along r).
+        constexpr int p = b == 0 ? 1 : 0, r = b == 2 ? 1 : 2;
+        const double sg = side ? 1.0 : -1.0;
+        double v[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (!ln.ok(q)) continue;
+            F s0 = F(0), sp = F(0), sr = F(0);
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int sgn[3] = {o >> 2, (o >> 1) & 1, o & 1};
+                if (sgn[b] != side) continue;  // not leaving through FACE
+                const F x = fo[o][q];
+                s0 += x;
+                sp += sgn[p] ? x : -x;
+                sr += sgn[r] ? x : -x;
+            }
+            int a3[3];
+            ln.axes(q, a3[0], a3[1], a3[2]);
+            const double ab[3] = {(a3[0] + 0.5) * a.g.dv[0], (a3[1] + 0.5) * a.g.dv[1], (a3[2] + 0.5) * a.g.dv[2]};
+            const double S0 = double(s0), Sp = double(sp), Sr = double(sr);
+            const double xb = sg * ab[b];  // xi . e_b of the leaving values
+            v[0] += xb * S0;
+            v[1 + b] += xb * xb * S0;
+            v[1 + p] += xb * ab[p] * Sp;
+            v[1 + r] += xb * ab[r] * Sr;
+            v[4] += 0.5 * xb * ((ab[0] * ab[0] + ab[1] * ab[1]) + ab[2] * ab[2]) * S0;
+        }
+        block_sum<T, 5>(v, red);
+        if (threadIdx.x == 0)
+            for (int x = 0; x < 5; ++x) h.face[(c * 6 + FACE) * 5 + x] = a.g.w * v[x];
+    }
     template <typename F, int NH, int T>
     __device__ __forceinline__ void apply(const StepArgs &a, const CellView &cell, int64_t c,
                                           const Regs<F, NH, T> &fo, double *red) const {
-        using L = Lane<NH, T>;
-        constexpr int S = L::S;
-        const L ln;
 #pragma nounroll
         for (int f = 0; f < 6; ++f) {
             const int ty = cell.type_rt(f);
@@ -646,32 +688,14 @@ struct HybHook {
             bool fluid_nb = false;
             for (int q = 0; q < k; ++q) fluid_nb |= h.mask[cell.nbr_rt(f, q)] == 0;
             if (!fluid_nb) continue;
-            const int b = f >> 1, side = f & 1;
-            double v[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                if (!ln.ok(q)) continue;
-                int a3[3];
-                ln.axes(q, a3[0], a3[1], a3[2]);
-#pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    const int sx = o >> 2, sy = (o >> 1) & 1, sz = o & 1;
-                    const int sbb = b == 0 ? sx : b == 1 ? sy : sz;
-                    if (sbb != side) continue;  // not leaving through f
-                    const double x0 = (sx ? 1.0 : -1.0) * (a3[0] + 0.5) * a.g.dv[0];
-                    const double x1 = (sy ? 1.0 : -1.0) * (a3[1] + 0.5) * a.g.dv[1];
-                    const double x2 = (sz ? 1.0 : -1.0) * (a3[2] + 0.5) * a.g.dv[2];
-                    const double xn = (b == 0 ? x0 : b == 1 ? x1 : x2) * double(fo[o][q]);
-                    v[0] += xn;
-                    v[1] += xn * x0;
-                    v[2] += xn * x1;
-                    v[3] += xn * x2;
-                    v[4] += 0.5 * xn * ((x0 * x0 + x1 * x1) + x2 * x2);
-                }
+            switch (f) {
+            case 0: face_flux<0, F, NH, T>(a, c, fo, red); break;
+            case 1: face_flux<1, F, NH, T>(a, c, fo, red); break;
+            case 2: face_flux<2, F, NH, T>(a, c, fo, red); break;
+            case 3: face_flux<3, F, NH, T>(a, c, fo, red); break;
+            case 4: face_flux<4, F, NH, T>(a, c, fo, red); break;
+            default: face_flux<5, F, NH, T>(a, c, fo, red); break;
             }
-            block_sum<T, 5>(v, red);
-            if (threadIdx.x == 0)
-                for (int x = 0; x < 5; ++x) h.face[(c * 6 + f) * 5 + x] = a.g.w * v[x];
         }
     }
 };
