@@ -710,7 +710,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
 // first); each reads its instance's arguments with scalar loads.
 template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step_batch(
-    const StepArgs *inst, const uint32_t *wg_end, int n_inst, int xcd_log2) {
+    const StepArgs *__restrict__ inst, const uint32_t *__restrict__ wg_end, int n_inst, int xcd_log2) {
     __shared__ StepSmem<F, NH, T> sm;
     const uint32_t b = remap_cell(blockIdx.x, gridDim.x, xcd_log2);
     cuint32_t *we = as_const_space(wg_end);
@@ -721,13 +721,10 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
         else lo = mid + 1;
     }
     const uint32_t start = lo == 0 ? 0u : we[lo - 1];
-    // the instance's arguments in LDS (a private copy would live in scratch
-    // memory: the step indexes some of its fields with runtime values)
-    __shared__ StepArgs a;
-    static_assert(sizeof(StepArgs) % 4 == 0 && sizeof(StepArgs) / 4 <= T, "argument words");
-    if (threadIdx.x < sizeof(StepArgs) / 4)
-        reinterpret_cast<uint32_t *>(&a)[threadIdx.x] = reinterpret_cast<const uint32_t *>(inst + lo)[threadIdx.x];
-    __syncthreads();
+    // the instance's arguments read in place (uniform address: scalar loads;
+    // a private copy would live in scratch memory, an LDS copy costs an LDS
+    // read at every use)
+    const StepArgs &a = inst[lo];
     const int64_t c = int64_t(b - start);
     if (needs_correction(a.cells, c)) step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
     else step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
