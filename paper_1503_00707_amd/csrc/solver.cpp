@@ -152,6 +152,12 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         s->cfg.xcd_group = 512;
         s->cfg.nt_store = 1;
     }
+    if (nh == 12 && fp64) {
+        s->cfg.threads = 576;
+        s->cfg.wpe = 30;
+        s->cfg.xcd_group = 64;
+        s->cfg.nt_store = 1;
+    }
     s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
     s->has_wall = m->n_faces[DVM_FACE_WALL] > 0;
     const size_t fs = fp64 ? 8 : 4;
