@@ -8,7 +8,7 @@ import pytest
 
 from paper_1503_00707_amd import dvm as D
 from paper_1503_00707_amd import inputs as I
-from tests.gpu_common import Case, balanced, gpu_run, gpu_solver, moment_errors, oracle_run
+from tests.gpu_common import Case, balanced, gpu_run, gpu_solver, moment_errors, oracle_run, prim_for
 
 pytestmark = pytest.mark.gpu
 
@@ -224,3 +224,76 @@ def test_split_launches_equal_single_launch_bitwise(precision, irr):
     o = oracle_run(case, 3)
     err = moment_errors(out[0][1], o["mom"])
     assert np.all(err <= (FP64_TOL if precision == D.PREC_FP64 else FP32_TOL)), err
+
+
+# --- degenerate and edge cases -------------------------------------------
+
+@pytest.mark.parametrize("nv", [4, 8])
+@pytest.mark.parametrize("scheme", [I.SCHEME_UPWIND1, I.SCHEME_MUSCL])
+@pytest.mark.parametrize("precision", [D.PREC_FP64, D.PREC_FP32])
+def test_single_cell_periodic_domain(nv, scheme, precision):
+    """One leaf whose six faces wrap onto itself (the smallest mesh), from a
+    non-Maxwellian state: the transport of eq. 2 cancels exactly and the step
+    is the BGK relaxation alone; the smallest velocity grid (4^3) included."""
+    import torch
+    from oracle import oracle as O
+    f = I.uniform_forest((1, 1, 1), 0)
+    case = Case(f, nv, 3.0, scheme=scheme, tau=0.05, fields="uniform")
+    rng = np.random.default_rng(nv + 10 * scheme)
+    x = 0.05 + rng.random((1, nv ** 3))
+    om = O.Mesh(f)
+    op = O.make_params((nv,) * 3, (-3.0,) * 3, (3.0,) * 3, scheme=scheme, tau_or_kn=0.05)
+    os_ = O.Solver(om, op)
+    os_.set_f(x)
+    dt = os_.dt_cfl(0.5)
+    assert os_.step(dt, 4) == 0
+    dm, s = gpu_solver(case, precision)
+    s.set_f_canonical(x)
+    s.step(4, dt=dt)
+    torch.cuda.synchronize()
+    fo, fg = os_.get_f(), s.f_canonical().double().cpu().numpy()
+    xf = x.astype(np.float32).astype(np.float64) if precision == D.PREC_FP32 else x
+    tol = FP64_TOL if precision == D.PREC_FP64 else 1e-5
+    assert np.abs(fg - fo).max() <= tol * np.abs(fo).max()
+    err = moment_errors(s.moments().cpu().numpy(), os_.moments())
+    assert np.all(err <= (FP64_TOL if precision == D.PREC_FP64 else FP32_TOL)), err
+    # the relaxation moves f toward the Maxwellian, it does not leave it
+    assert np.abs(fg - xf).max() > 1e-3
+    rc, _, bad, n = s.check()
+    assert rc == 0 and not bad and n == 4
+
+
+@pytest.mark.parametrize("scheme", [I.SCHEME_UPWIND1, I.SCHEME_MUSCL])
+def test_smallest_velocity_grid_octree_open_and_wall_fp64(scheme):
+    """4^3 velocities (one node per octant axis) on an octree with inflow,
+    outflow, wall and periodic faces"""
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)
+    f = balanced(I.random_forest(11, (2, 2, 2), 3, 0.25, bc))
+    case = Case(f, 4, 3.5, scheme=scheme, tau=0.04, inflow=(1.0, 0.6, 0.0, 0.1, 1.0), t_wall=1.3,
+                fields="sines", field_args={"seed": 44})
+    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
+
+
+def test_xcd_grouping_is_bitwise_neutral_with_ragged_tail():
+    """The XCD-aware order of the workgroups is a bijection of the cells,
+    with the cells past the last whole round of groups left in place; every
+    cell's arithmetic is the same whichever order runs it."""
+    import torch
+    f = balanced(I.random_forest(12, (8, 8, 8), 2, 0.3))  # 6,791 cells
+    case = Case(f, 24, 6.0, tau_mode=I.TAU_HS, tau=0.02, fields="sines", field_args={"seed": 12})
+    dm, s = gpu_solver(case, D.PREC_FP32)
+    n = s.n
+    assert n > 8 * 512 and n % (8 * 64) != 0 and n % (8 * 512) != 0
+    dt = s.dt(case.cfl)
+    prim = prim_for(case, dm.tables()["input"])
+    ref = None
+    for g in (1, 8, 64, 512):
+        s.set_shape(192, 31, g, 1)
+        s.init_maxwellian(prim)
+        s.step(2, dt=dt)
+        torch.cuda.synchronize()
+        out = (s.f_canonical().cpu().numpy(), s.moments().cpu().numpy())
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), g

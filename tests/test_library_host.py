@@ -101,6 +101,9 @@ def test_argument_errors():
     with pytest.raises(D.DvmError) as e:
         D.Mesh(dataclasses.replace(g, bc=(I.PERIODIC, I.OUTFLOW) + (I.PERIODIC,) * 4))
     assert e.value.code == D.ERR_ARG
+    with pytest.raises(D.DvmError) as e:  # no leaves at all
+        D.Mesh(dataclasses.replace(g, level=g.level[:0], ijk=g.ijk[:0]))
+    assert e.value.code == D.ERR_ARG
 
 
 def test_solver_argument_errors_host_only():
