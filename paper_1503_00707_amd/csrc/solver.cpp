@@ -152,6 +152,14 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         s->cfg.xcd_group = 512;
         s->cfg.nt_store = 1;
     }
+    if ((nh == 6 || nh == 8) && !fp64) {
+        // 12^3 and 16^3: per-cell fixed work (reductions, the Maxwellian
+        // system) dominates, and two waves per cell keep more cells in flight
+        s->cfg.threads = 128;
+        s->cfg.wpe = nh == 6 ? 60 : 50;
+        s->cfg.xcd_group = 64;
+        s->cfg.nt_store = 1;
+    }
     if (nh == 12 && fp64) {
         s->cfg.threads = 576;
         s->cfg.wpe = 30;

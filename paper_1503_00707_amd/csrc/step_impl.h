@@ -890,7 +890,11 @@ __global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelG
     X(2, 64, 4, 0)          \
     X(4, 64, 5, 0)          \
     X(6, 256, 6, 0)         \
+    X(6, 64, 4, 0)          \
+    X(6, 128, 6, 0)         \
     X(8, 256, 5, 0)         \
+    X(8, 64, 3, 0)          \
+    X(8, 128, 5, 0)         \
     X(8, 256, 5, 1)         \
     X(8, 512, 4, 0)         \
     X(12, 192, 3, 1)        \
