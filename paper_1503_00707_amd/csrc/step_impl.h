@@ -745,10 +745,15 @@ template <typename F, int NH>
 __global__ __launch_bounds__(256) void k_face(StepArgs a) {
     constexpr int B = NH * NH * NH;
     constexpr int64_t NV = 8 * B;
+    constexpr int T = 256;
+    // velocities per thread in one batch: every load of a batch is issued
+    // before the first is used, so a thread has 7-25 loads in flight instead
+    // of one velocity's
+    constexpr int U = 6;
     const int64_t c = blockIdx.x;
     const CellView cell(a.cells, c);
-    const F *fin = static_cast<const F *>(a.f_in);
-    F *face = static_cast<F *>(const_cast<void *>(a.face));
+    const F *__restrict__ fin = static_cast<const F *>(a.f_in);
+    F *__restrict__ face = static_cast<F *>(const_cast<void *>(a.face));
     const F *own = fin + c * NV;
     const double h = a.h0 / double(1 << cell.level());
     const bool wall = cell.flags() & 1;
@@ -774,27 +779,48 @@ __global__ __launch_bounds__(256) void k_face(StepArgs a) {
             src[f][0] = static_cast<const F *>(a.ghost_in);
         }
     }
-    for (int64_t v = threadIdx.x; v < NV; v += 256) {
-        const int o = int(v / B);
-        const F fc = own[v];
+    for (int64_t v0 = threadIdx.x; v0 < NV; v0 += int64_t(U) * T) {
+        F fc[U], nm[U][6];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            F sig = F(0);
-            if (!wall) {
-                F nm[2];
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + int64_t(u) * T;
+            fc[u] = v < NV ? own[v] : F(0);
+        }
+        if (!wall) {
 #pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    const int f = 2 * b + side;
-                    F x = src[f][0][v];
-                    if (cnt[f] == 4) x = F(0.25) * (((x + src[f][1][v]) + src[f][2][v]) + src[f][3][v]);
-                    nm[side] = x;
+            for (int f = 0; f < 6; ++f) {
+                if (cnt[f] == 4) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int64_t v = v0 + int64_t(u) * T;
+                        nm[u][f] = v < NV ? F(0.25) * (((src[f][0][v] + src[f][1][v]) + src[f][2][v]) + src[f][3][v])
+                                          : F(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int64_t v = v0 + int64_t(u) * T;
+                        nm[u][f] = v < NV ? src[f][0][v] : F(0);
+                    }
                 }
-                const F sl = (fc - nm[0]) / dist[2 * b], sr = (nm[1] - fc) / dist[2 * b + 1];
-                sig = sl * sr <= F(0) ? F(0) : (fabs(sl) < fabs(sr) ? sl : sr);
             }
-            const int sb = b == 0 ? (o >> 2) : b == 1 ? ((o >> 1) & 1) : (o & 1);
-            const F half = F(sb ? 0.5 * h : -0.5 * h);
-            face[(b * a.n_cells + c) * NV + v] = fc + half * sig;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + int64_t(u) * T;
+            if (v >= NV) continue;
+            const int o = int(v / B);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                F sig = F(0);
+                if (!wall) {
+                    const F sl = (fc[u] - nm[u][2 * b]) / dist[2 * b], sr = (nm[u][2 * b + 1] - fc[u]) / dist[2 * b + 1];
+                    sig = sl * sr <= F(0) ? F(0) : (fabs(sl) < fabs(sr) ? sl : sr);
+                }
+                const int sb = b == 0 ? (o >> 2) : b == 1 ? ((o >> 1) & 1) : (o & 1);
+                const F half = F(sb ? 0.5 * h : -0.5 * h);
+                face[(b * a.n_cells + c) * NV + v] = fc[u] + half * sig;
+            }
         }
     }
 }
