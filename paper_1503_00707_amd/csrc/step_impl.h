@@ -52,10 +52,33 @@ __device__ __forceinline__ cF<T> *as_const_space(const T *p) {
     return (cF<T> *)p;  // generic -> constant address space (a C cast: no C++ cast crosses spaces)
 }
 
+// A double moved across lanes by a DPP pattern (both 32-bit halves); the
+// patterns used here take every source lane from the same row of 16.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(u)), CTRL, 0xf, 0xf, false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_mov_dpp(int(uint32_t(u >> 32)), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u)), lane));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(u >> 32)), lane));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active); every lane receives
+// the same total.  Within a row of 16 lanes: pairs (lane ^ 1), pairs of
+// pairs (lane ^ 2), then the mirrored half-row and the mirrored row, each a
+// commutative exchange, so all 16 lanes hold the identical row sum; the four
+// row sums are then read as uniform values and added in a fixed order.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // Sum K values over the workgroup; every thread receives the same totals in
