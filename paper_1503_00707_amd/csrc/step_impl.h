@@ -68,6 +68,15 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
 }
 
+// A double read from another lane of the wave (any index; taken modulo 64).
+__device__ __forceinline__ double shfl_f64(double v, int src) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int addr = (src & 63) << 2;
+    const uint32_t lo = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_ds_bpermute(addr, int(uint32_t(u >> 32))));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
 // Sum over the 64 lanes of a wave (every lane active); every lane receives
 // the same total.  Within a row of 16 lanes: pairs (lane ^ 1), pairs of
 // pairs (lane ^ 2), then the mirrored half-row and the mirrored row, each a
@@ -249,7 +258,6 @@ template <typename F, int NH>
 struct MaxwellSmem {
     static constexpr int N = 2 * NH;
     double S[15];
-    double A[5][6];  // augmented Gram system
     double d[5];
     double C;
     double g[3][N];
@@ -278,8 +286,8 @@ __device__ inline double gram_entry(int i, int j, const double *X, const double 
 // those of the raw Maxwellian.  Every entry of G is a product of 1D sums
 // S_b,p = dv_b sum_k c_k^p g_k, so the cost per cell is O(N), not O(N^3).
 // The 5x6 augmented system is eliminated Gauss-Jordan style by 30 lanes of
-// the first wave through LDS (one element per lane; G is symmetric positive
-// definite, so no pivoting).  tab[0] carries C * mfac, so that the table
+// the first wave, one element per lane in a register (G is symmetric
+// positive definite, so no pivoting).  tab[0] carries C * mfac, so that the table
 // product is mfac * Mt.
 template <typename F, int NH, int T>
 __device__ __forceinline__ void maxwell_solve(MaxwellSmem<F, NH> &sm, double rho, const double u[3], double Tt,
@@ -312,24 +320,25 @@ __device__ __forceinline__ void maxwell_solve(MaxwellSmem<F, NH> &sm, double rho
         const bool el = lane < 30;
         const double x2 = 6.283185307179586476925286766559 * Tt;
         const double C = rho / (x2 * sqrt(x2));
+        // lane 6i + j holds A[i][j]; each elimination step reads the pivot
+        // row and column from the lanes that hold them (no LDS round trip)
+        double x = 0.0;
         if (el) {
-            double v;
-            if (j < 5) v = gram_entry(i, j, &sm.S[0], &sm.S[5], &sm.S[10]);
+            if (j < 5) x = gram_entry(i, j, &sm.S[0], &sm.S[5], &sm.S[10]);
             else {
                 const double t = (i == 0 ? 1.0 : i == 4 ? 3.0 : 0.0) * (rho / C);
-                v = t - gram_entry(i, 0, &sm.S[0], &sm.S[5], &sm.S[10]);
+                x = t - gram_entry(i, 0, &sm.S[0], &sm.S[5], &sm.S[10]);
             }
-            sm.A[i][j] = v;
         }
-        __builtin_amdgcn_wave_barrier();
+#pragma unroll
         for (int k = 0; k < 5; ++k) {
-            double nv = 0.0;
-            if (el && i != k) nv = sm.A[i][j] - sm.A[i][k] / sm.A[k][k] * sm.A[k][j];
-            __builtin_amdgcn_wave_barrier();
-            if (el && i != k) sm.A[i][j] = nv;
-            __builtin_amdgcn_wave_barrier();
+            const double akk = readlane_f64(x, 7 * k);
+            const double aik = shfl_f64(x, 6 * i + k);
+            const double akj = shfl_f64(x, 6 * k + j);
+            if (el && i != k) x = x - aik / akk * akj;
         }
-        if (lane < 5) sm.d[lane] = sm.A[lane][5] / sm.A[lane][lane];
+        const double diag = shfl_f64(x, 7 * lane), rhs = shfl_f64(x, 6 * lane + 5);
+        if (lane < 5) sm.d[lane] = rhs / diag;
         if (lane == 0) sm.C = C;
     }
     __syncthreads();
