@@ -782,7 +782,9 @@ __global__ __launch_bounds__(256) void k_face(StepArgs a) {
     // before the first is used, so a thread has 7-25 loads in flight instead
     // of one velocity's
     constexpr int U = 6;
-    const int64_t c = blockIdx.x;
+    // the XCD-aware order of the step kernel: a face neighbour's row, read by
+    // several workgroups, is more often still in the same L2
+    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const CellView cell(a.cells, c);
     const F *__restrict__ fin = static_cast<const F *>(a.f_in);
     F *__restrict__ face = static_cast<F *>(const_cast<void *>(a.face));
