@@ -1,0 +1,33 @@
+"""Host-side checks of bench.py: the one-GPU contract and the rule that
+stored HBM counters are reported only for the kernel source they were
+taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_stored_traffic_follows_the_kernel_source_hash(tmp_path, monkeypatch):
+    good = {"kernel": "k_step", "source_sha256": bench.kernel_source_hash(), "read_bytes": 300, "write_bytes": 100,
+            "per": "launch"}
+    p = tmp_path / "profile.md"
+    p.write_text("# summary\n\ntraffic_json: " + json.dumps(good) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", "profile.md")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: good["source_sha256"])
+    t = bench.measured_traffic(200)
+    assert t["total_bytes"] == 400 and t["vs_algorithmic"] == 2.0
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
+    assert bench.measured_traffic(200) is None
+
