@@ -274,13 +274,15 @@ def test_smallest_velocity_grid_octree_open_and_wall_fp64(scheme):
     _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
 
 
-def test_xcd_grouping_is_bitwise_neutral_with_ragged_tail():
-    """The XCD-aware order of the workgroups is a bijection of the cells,
-    with the cells past the last whole round of groups left in place; every
-    cell's arithmetic is the same whichever order runs it."""
+@pytest.mark.parametrize("scheme", [I.SCHEME_UPWIND1, I.SCHEME_MUSCL])
+def test_xcd_grouping_is_bitwise_neutral_with_ragged_tail(scheme):
+    """The XCD-aware order of the workgroups (step kernel, and the MUSCL
+    face-value kernel) is a bijection of the cells, with the cells past the
+    last whole round of groups left in place; every cell's arithmetic is the
+    same whichever order runs it."""
     import torch
     f = balanced(I.random_forest(12, (8, 8, 8), 2, 0.3))  # 6,791 cells
-    case = Case(f, 24, 6.0, tau_mode=I.TAU_HS, tau=0.02, fields="sines", field_args={"seed": 12})
+    case = Case(f, 24, 6.0, scheme=scheme, tau_mode=I.TAU_HS, tau=0.02, fields="sines", field_args={"seed": 12})
     dm, s = gpu_solver(case, D.PREC_FP32)
     n = s.n
     assert n > 8 * 512 and n % (8 * 64) != 0 and n % (8 * 512) != 0
