@@ -21,7 +21,21 @@ def _uniform16_v8():
     return Case(w.forest, 8, 4.5, tau=0.1, fields="sine_rho", field_args={"a": 0.1})
 
 
+def sums_errors(g, ref, mom_ref):
+    """global FP64 sums sum_c V_c (rho, rho u, E): per-component error over
+    (total mass, total mass sqrt(max T) for the momenta, total energy)"""
+    rho = mom_ref[0]
+    u = mom_ref[1:4] / rho
+    T = (2 * mom_ref[4] / rho - (u * u).sum(0)) / 3
+    su = abs(ref[0]) * float(np.sqrt(T.max()))
+    scale = np.array([abs(ref[0]), su, su, su, abs(ref[4])])
+    return np.abs(np.asarray(g) - ref) / scale
+
+
 def _compare(case, steps, precision, tol, f_tol=None, engine=None):
+    """moments (and the step's own moments buffer), the global sums reported
+    by dvm_check and f against the oracle.  FP32 storage: f within 2e-5 of
+    max |f| unless f_tol says otherwise."""
     o = oracle_run(case, steps)
     g = gpu_run(case, steps, precision, engine)
     assert o["rc"] == 0 and g["rc"] == 0
@@ -32,6 +46,12 @@ def _compare(case, steps, precision, tol, f_tol=None, engine=None):
     # the moments written by the step (post-transport, conserved by the collision)
     err_step = moment_errors(g["mom_step"], o["mom"])
     assert np.all(err_step <= max(tol, 1e-12)), err_step
+    # global conservation sums (dvm_check) against the oracle's
+    es = sums_errors(g["sums"], o["sums"], o["mom"])
+    print("global sums errors", es)
+    assert np.all(es <= tol), es
+    if f_tol is None and precision == D.PREC_FP32:
+        f_tol = FP32_TOL
     if f_tol is not None:
         ef = np.abs(g["f"] - o["f"]).max() / np.abs(o["f"]).max()
         print("f error", ef)
