@@ -279,6 +279,60 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
 int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t wpe_irr, int32_t *previous);
 
 /*
+ * dvm_tune -- project autotuner for one solver (fused engine): time every
+ * compiled step shape x XCD cell grouping {1, 8, 64, 512} x store kind (plain
+ * or non-temporal) with reps trial steps on the solver's own state, keep the
+ * fastest (dvm_tune_get reports it).  cache_path (may be NULL) names a text
+ * file of tuned shapes, one line per key ("step", GPU architecture, N/2,
+ * precision, scheme): a key found there is applied without timing
+ * (*from_cache = 1, may be NULL); a timed key is added or replaced (the file
+ * is rewritten through a temporary and renamed).  The trial steps read the
+ * current state and write the other state buffer and the moments buffer; the
+ * moments are then recomputed from the current state (within rounding of the
+ * step's own values).  Synchronises.  DVM_ERR_UNSUPPORTED for the deferred
+ * engine or while fluid cells of a hybrid step hold no f; DVM_ERR_ARG if the
+ * cache cannot be written.
+ */
+int dvm_tune(dvm_solver *s, const char *cache_path, int32_t reps, int32_t *from_cache, void *stream);
+
+/*
+ * dvm_tune_cache_get / dvm_tune_cache_put -- host-only access to a tuner
+ * cache file (to inspect or pre-seed it): kind "step" or "batch", arch as
+ * reported by the device (e.g. "gfx950"), N/2, precision (fp64 != 0), scheme;
+ * shape = {threads, waves-per-EU variant, XCD cell grouping, non-temporal
+ * stores}, ms the time per step the tuner measured.  *found = 0 if the key
+ * is absent (shape and ms untouched).  The file is one text line per key,
+ * "<kind> <arch> nh=<N/2> fp64=<0|1> scheme=<0|1> | threads=<t> wpe=<w>
+ * xcd_group=<g> nt_store=<0|1> ms=<time>"; unreadable lines are ignored.
+ */
+int dvm_tune_cache_get(const char *path, const char *kind, const char *arch, int32_t nh, int32_t fp64,
+                       int32_t scheme, int32_t shape[4], double *ms, int32_t *found);
+int dvm_tune_cache_put(const char *path, const char *kind, const char *arch, int32_t nh, int32_t fp64,
+                       int32_t scheme, const int32_t shape[4], double ms);
+
+/*
+ * Checkpoint and restart.
+ * dvm_save -- write the solver's state to the file `path` (through
+ * `path`.tmp, then renamed): a header (velocity grid, precision, scheme,
+ * steps taken, root lattice, domain boundary kinds), the leaf list in cell
+ * order (Morton key, level, i, j, k), f in the canonical velocity order and
+ * the storage precision, the FP64 moments buffer, the hybrid step's previous
+ * mask (hybrid solvers), and, if net != NULL, the network's parameter block
+ * and Adam state; an FNV-1a 64-bit checksum of all of it at the end.  The
+ * other state buffer serves as staging (its contents are replaced).
+ * Synchronises the stream.
+ * dvm_load -- read such a file into a solver built on the same leaf list,
+ * velocity grid, precision and scheme (else DVM_ERR_ARG, before any device
+ * write); if net != NULL the file must hold a network, which replaces net's
+ * parameters and Adam state.  Stepping on after dvm_load gives bitwise the
+ * steps the saved solver would have taken with the same kernel shape.
+ * A checksum mismatch is reported as DVM_ERR_ARG after the state was
+ * overwritten (the solver's state is then not valid).
+ */
+int dvm_save(dvm_solver *s, const dvm_mlp *net, const char *path, void *stream);
+int dvm_load(dvm_solver *s, dvm_mlp *net, const char *path, void *stream);
+
+/*
  * Batched steps (many independent flow instances in one graph launch).
  *
  * dvm_batch_create -- group n bound solvers (same storage precision, first
@@ -302,6 +356,9 @@ int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t w
  * launches on the batch's own data and keep the fastest.  The state the
  * batch advances is unchanged (trial steps write only the next buffers; the
  * moments are recomputed from the current state afterwards).  Synchronises.
+ * cache_path (may be NULL): a group whose key ("batch", GPU architecture,
+ * N/2, precision) is in the tuner cache file (the format of dvm_tune) takes
+ * the stored shape without timing; timed groups are added to the file.
  * dvm_batch_info -- group < 0: *n_inst = number of groups; otherwise the
  * group's velocity half-size NH (N = 2 NH), instance count, total cells and
  * chosen shape (tuned_ms: best time per launch from the last tuning, or 0).
@@ -310,7 +367,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int32_t n, double cfl, dvm_batc
 int dvm_batch_workspace_bytes(const dvm_batch *b, size_t *bytes);
 int dvm_batch_bind(dvm_batch *b, void *ws);
 int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream);
-int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream);
+int dvm_batch_tune(dvm_batch *b, int32_t reps, const char *cache_path, void *stream);
 int dvm_batch_info(const dvm_batch *b, int32_t group, int32_t *nh, int32_t *n_inst, int64_t *n_cells,
                    int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store, double *tuned_ms);
 void dvm_destroy_batch(dvm_batch *b);
@@ -363,7 +420,13 @@ void dvm_destroy_batch(dvm_batch *b);
  * a non-periodic domain face stay kinetic.  Needs params.hybrid = 1, the
  * fused engine and first order (DVM_ERR_UNSUPPORTED otherwise).  With every
  * cell kinetic it is dvm_step.  After hybrid steps the moments buffer is the
- * state of fluid cells; dvm_moments recomputes from f (kinetic cells only).
+ * state of fluid cells (whose f rows are stale): dvm_moments then recomputes
+ * kinetic cells from f and copies fluid cells' conserved moments, and must be
+ * given another output than the moments buffer (DVM_ERR_ARG); dvm_step,
+ * dvm_batch_create and dvm_batch_step refuse such a solver
+ * (DVM_ERR_UNSUPPORTED) until a new state (dvm_init_maxwellian,
+ * dvm_f_from_canonical) restores f everywhere; hybrid steps with an all-ones
+ * mask continue it with every cell kinetic.
  */
 #define DVM_MLP_WEIGHTS 4929
 #define DVM_MLP_PARAMS 4949

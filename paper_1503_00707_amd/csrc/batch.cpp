@@ -150,6 +150,8 @@ int dvm_batch_create(dvm_solver *const *solvers, int32_t n, double cfl, dvm_batc
         if (!s) return fail(DVM_ERR_ARG, "solver %d is NULL", i);
         if (s->fp64 != solvers[0]->fp64) return fail(DVM_ERR_UNSUPPORTED, "a batch has one storage precision");
         if (s->muscl) return fail(DVM_ERR_UNSUPPORTED, "batched steps are first order");
+        if (s->hybrid_fluid)
+            return fail(DVM_ERR_UNSUPPORTED, "solver %d holds fluid cells from hybrid steps (their f is stale)", i);
         if (uint64_t(s->n) >= (uint64_t(1) << 31)) return fail(DVM_ERR_UNSUPPORTED, "instance too large");
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(DVM_ERR_ARG, "solver %d listed twice", i);
@@ -224,6 +226,8 @@ int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream) {
     hipStream_t st = S(stream);
     for (auto *s : b->s) {
         if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "every solver must be bound and uploaded");
+        if (s->hybrid_fluid)
+            return fail(DVM_ERR_UNSUPPORTED, "a solver holds fluid cells from hybrid steps (their f is stale)");
         if (s->relax_pending) {
             hipError_t e = solver_make_plain(s, st);
             if (e != hipSuccess) return hip_fail(e, "state conversion");
@@ -251,7 +255,7 @@ int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream) {
     return DVM_OK;
 }
 
-int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream) {
+int dvm_batch_tune(dvm_batch *b, int32_t reps, const char *cache_path, void *stream) {
     clear_error();
     if (!b) return fail(DVM_ERR_ARG, "null batch");
     if (!b->ws) return fail(DVM_ERR_WORKSPACE, "call dvm_batch_bind first");
@@ -259,6 +263,8 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream) {
     hipStream_t st = S(stream);
     for (auto *s : b->s) {
         if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "every solver must be bound and uploaded");
+        if (s->hybrid_fluid)
+            return fail(DVM_ERR_UNSUPPORTED, "a solver holds fluid cells from hybrid steps (their f is stale)");
         if (s->relax_pending) {
             hipError_t e = solver_make_plain(s, st);
             if (e != hipSuccess) return hip_fail(e, "state conversion");
@@ -272,7 +278,18 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream) {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(DVM_ERR_DEVICE, "events");
     const int groups[3] = {1, 8, 64};
     int rc = DVM_OK;
+    bool timed = false;
     for (auto &g : b->groups) {
+        const TuneKey key{"batch", g.nh, b->fp64 ? 1 : 0, 0};
+        StepConfig cached{};
+        double cached_ms = 0.0;
+        if (tune_cache_get(cache_path, key, &cached, &cached_ms) && have_kernel(g.nh, cached.threads, cached.wpe) &&
+            cached.xcd_group >= 1 && cached.xcd_group <= 4096 && !(cached.xcd_group & (cached.xcd_group - 1))) {
+            g.cfg = StepConfig{cached.threads, cached.xcd_group, cached.nt_store != 0, cached.wpe, 0};
+            g.tuned_ms = cached_ms;
+            continue;
+        }
+        timed = true;
         // trial steps read the current buffers and write only the next ones
         // (and the moments), so the state the batch advances is unchanged
         int thr[64], wpe[64];
@@ -301,16 +318,18 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, void *stream) {
                 }
         g.cfg = best_cfg;
         g.tuned_ms = best;
+        if (rc == DVM_OK) rc = tune_cache_put(cache_path, key, best_cfg, best);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    b->drop_graphs();  // new kernel shapes: re-record at the next step
+    if (!timed) return DVM_OK;
     // the trial steps overwrote the moments: restore those of the current state
     for (auto *s : b->s) {
         hipError_t e = launch_moments(s->fp64, s->f[s->cur], s->mom, s->n, s->g, st);
         if (e != hipSuccess) return hip_fail(e, "moments");
     }
-    b->drop_graphs();  // new kernel shapes: re-record at the next step
     return DVM_OK;
 }
 

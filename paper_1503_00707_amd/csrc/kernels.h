@@ -115,6 +115,7 @@ hipError_t launch_adam(float *params, float *m, float *v, const float *grad, flo
 hipError_t launch_norm_stats(const float *x, int64_t n, float *params, hipStream_t st);
 hipError_t launch_mask_eff(const uint8_t *in, uint8_t *out, const DevCell *cells, int64_t n, hipStream_t st);
 hipError_t launch_hybrid(bool fp64, const StepArgs &a, const HybArgsPub &h, hipStream_t st);
+hipError_t launch_fluid_moments(const uint8_t *mask, const double *mom, double *out, int64_t n, hipStream_t st);
 
 // Deferred-collision engine (lazy_impl.h).
 struct UnitArgsPub {

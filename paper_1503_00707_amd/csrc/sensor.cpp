@@ -9,21 +9,6 @@
 
 using namespace dvm;
 
-struct dvm_mlp {
-    int64_t max_batch = 0;
-    float *params = nullptr;
-    char *ws = nullptr;
-    size_t off_m = 0, off_v = 0, off_grad = 0, off_rec = 0, off_lpart = 0, off_loss = 0, ws_bytes = 0;
-    int64_t t = 0;  // Adam step count
-
-    float *m() const { return reinterpret_cast<float *>(ws + off_m); }
-    float *v() const { return reinterpret_cast<float *>(ws + off_v); }
-    float *grad() const { return reinterpret_cast<float *>(ws + off_grad); }
-    float *rec() const { return reinterpret_cast<float *>(ws + off_rec); }
-    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
-    double *loss() const { return reinterpret_cast<double *>(ws + off_loss); }
-};
-
 namespace {
 
 SensorArgsPub sensor_args(const dvm_solver *s) {
@@ -55,6 +40,11 @@ namespace dvm {
 hipError_t solver_reset_hybrid(dvm_solver *s, hipStream_t st) {
     if (!s->hybrid || !s->ws) return hipSuccess;
     return hipMemsetAsync(hyb_prev(s), 1, size_t(s->n), st);
+}
+uint8_t *solver_hybrid_prev(const dvm_solver *s) { return s->hybrid && s->ws ? hyb_prev(s) : nullptr; }
+hipError_t solver_fluid_moments(const dvm_solver *s, double *out, hipStream_t st) {
+    if (!s->hybrid_fluid) return hipSuccess;
+    return launch_fluid_moments(hyb_mask(s), s->mom, out, s->n, st);
 }
 }  // namespace dvm
 

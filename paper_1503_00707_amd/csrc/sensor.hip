@@ -70,6 +70,11 @@ hipError_t launch_mask_eff(const uint8_t *in, uint8_t *out, const DevCell *cells
     return hipGetLastError();
 }
 
+hipError_t launch_fluid_moments(const uint8_t *mask, const double *mom, double *out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(impl::k_fluid_moments, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, mask, mom, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_hybrid(bool fp64, const StepArgs &a, const HybArgsPub &h, hipStream_t st) {
     impl::HybArgs hh;
     __builtin_memcpy(&hh, &h, sizeof hh);

@@ -747,6 +747,15 @@ __global__ __launch_bounds__(256) void k_fluid_update(StepArgs a, HybArgs h) {
     if (!(U[0] > 0.0) || !(2.0 * U[4] - k2 > 0.0)) *a.flag = 1;
 }
 
+// After hybrid steps the f rows of fluid cells are stale and their state is
+// the conserved moments U: copy U over what was recomputed from f.
+__global__ __launch_bounds__(256) void k_fluid_moments(const uint8_t *mask, const double *mom, double *out,
+                                                       int64_t n) {
+    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= n || mask[c]) return;
+    for (int x = 0; x < 5; ++x) out[x * n + c] = mom[x * n + c];
+}
+
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------

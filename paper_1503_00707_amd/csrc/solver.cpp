@@ -409,6 +409,9 @@ int dvm_moments(dvm_solver *s, double *out, void *stream) {
     clear_error();
     if (!s || !out) return fail(DVM_ERR_ARG, "null argument");
     if (!s->f[0]) return fail(DVM_ERR_WORKSPACE, "solver not bound");
+    if (s->hybrid_fluid && out == s->mom)
+        return fail(DVM_ERR_ARG, "after hybrid steps the moments buffer holds the fluid cells' state: pass "
+                                 "another output buffer");
     hipError_t e;
     if (s->relax_pending) {
         UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
@@ -417,6 +420,8 @@ int dvm_moments(dvm_solver *s, double *out, void *stream) {
     } else {
         e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
     }
+    // fluid cells of a hybrid step carry only their conserved moments
+    if (e == hipSuccess) e = solver_fluid_moments(s, out, S(stream));
     if (e != hipSuccess) return hip_fail(e, "moments");
     return DVM_OK;
 }

@@ -80,6 +80,22 @@ struct dvm_solver {
     const uint32_t *sel() const { return reinterpret_cast<const uint32_t *>(ws + off_sel); }
 };
 
+// The sensor network: host object over a caller-owned parameter block and
+// workspace (Adam moments, gradients, per-sample scratch).
+struct dvm_mlp {
+    int64_t max_batch = 0;
+    float *params = nullptr;
+    char *ws = nullptr;
+    size_t off_m = 0, off_v = 0, off_grad = 0, off_rec = 0, off_lpart = 0, off_loss = 0, ws_bytes = 0;
+    int64_t t = 0;  // Adam step count
+
+    float *m() const { return reinterpret_cast<float *>(ws + off_m); }
+    float *v() const { return reinterpret_cast<float *>(ws + off_v); }
+    float *grad() const { return reinterpret_cast<float *>(ws + off_grad); }
+    float *rec() const { return reinterpret_cast<float *>(ws + off_rec); }
+    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
+    double *loss() const { return reinterpret_cast<double *>(ws + off_loss); }
+};
 
 namespace dvm {
 // The state buffer holds f itself (applies a pending deferred relaxation).
@@ -89,4 +105,27 @@ StepArgs solver_step_args(const dvm_solver *s, double dt);
 double solver_max_speed_sum(const dvm_solver *s);
 // every cell kinetic again (a fresh state); no-op without the hybrid workspace
 hipError_t solver_reset_hybrid(dvm_solver *s, hipStream_t st);
+// fluid cells of the last hybrid step: out[5][n] := their conserved moments
+hipError_t solver_fluid_moments(const dvm_solver *s, double *out, hipStream_t st);
+// the hybrid step's mask of the previous step [n] (NULL without the hybrid workspace)
+uint8_t *solver_hybrid_prev(const dvm_solver *s);
+
+// Tuner cache: one line per (kind, GPU architecture, N/2, precision, scheme)
+// with the chosen kernel shape.  kind is "step" (one solver) or "batch".
+struct TuneKey {
+    const char *kind;
+    int nh;
+    int fp64;
+    int scheme;
+};
+// architecture name of the current device (e.g. "gfx950"), "" on failure
+std::string device_arch();
+// true and *cfg (threads, wpe, xcd_group, nt_store) if the cache holds the key
+bool tune_cache_get(const char *path, const TuneKey &k, StepConfig *cfg, double *ms);
+// add or replace the key's line; DVM_OK or a DVM_ERR_* (with the error text set)
+int tune_cache_put(const char *path, const TuneKey &k, const StepConfig &cfg, double ms);
+// the same for a named architecture
+bool tune_cache_get_arch(const char *path, const TuneKey &k, const std::string &arch, StepConfig *cfg, double *ms);
+int tune_cache_put_arch(const char *path, const TuneKey &k, const std::string &arch, const StepConfig &cfg,
+                        double ms);
 }  // namespace dvm

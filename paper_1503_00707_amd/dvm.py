@@ -32,6 +32,7 @@ EXPORTED = [
     "dvm_features", "dvm_labels", "dvm_mlp_create", "dvm_mlp_workspace_bytes", "dvm_mlp_bind",
     "dvm_mlp_set_normalization", "dvm_mlp_forward", "dvm_mlp_gradient", "dvm_mlp_adam", "dvm_mlp_train_step",
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
+    "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
 ]
 MLP_WEIGHTS, MLP_PARAMS = 4929, 4949
 
@@ -109,7 +110,14 @@ def lib():
         L.dvm_batch_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
         L.dvm_batch_bind.argtypes = [P, P]
         L.dvm_batch_step.argtypes = [P, C.c_int32, P]
-        L.dvm_batch_tune.argtypes = [P, C.c_int32, P]
+        L.dvm_batch_tune.argtypes = [P, C.c_int32, C.c_char_p, P]
+        L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
+        L.dvm_save.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, C.c_int32, C.c_int32, C.c_int32, P,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.dvm_tune_cache_put.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, C.c_int32, C.c_int32, C.c_int32, P,
+                                         C.c_double]
         L.dvm_batch_info.argtypes = [P, C.c_int32, P, P, P, P, P, P, P, P]
         L.dvm_destroy_batch.argtypes = [P]
         L.dvm_destroy_batch.restype = None
@@ -217,6 +225,22 @@ def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=
     return p
 
 
+def tune_cache_get(path, kind, arch, nh, fp64, scheme):
+    """(threads, wpe, xcd_group, nt_store), ms) stored for the key, or None"""
+    shape = np.zeros(4, np.int32)
+    ms = C.c_double(0)
+    found = C.c_int32(0)
+    _check(lib().dvm_tune_cache_get(os.fsencode(path), kind.encode(), arch.encode(), int(nh), int(fp64), int(scheme),
+                                    shape.ctypes.data, C.byref(ms), C.byref(found)), "dvm_tune_cache_get")
+    return (tuple(int(x) for x in shape), ms.value) if found.value else None
+
+
+def tune_cache_put(path, kind, arch, nh, fp64, scheme, shape, ms):
+    sh = np.ascontiguousarray(shape, np.int32)
+    _check(lib().dvm_tune_cache_put(os.fsencode(path), kind.encode(), arch.encode(), int(nh), int(fp64), int(scheme),
+                                    sh.ctypes.data, float(ms)), "dvm_tune_cache_put")
+
+
 class Solver:
     """Owns the torch device buffers of one solver and drives the C interface."""
 
@@ -287,6 +311,21 @@ class Solver:
         out = self.torch.empty((5, self.n), dtype=self.torch.float64, device="cuda")
         _check(lib().dvm_moments(self.h, out.data_ptr(), self.stream()), "dvm_moments")
         return out
+
+    def tune(self, cache_path=None, reps=2):
+        """time the compiled kernel shapes on this solver (dvm_tune); returns
+        True if the choice came from the tuner cache file"""
+        fc = C.c_int32(0)
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().dvm_tune(self.h, cp, int(reps), C.byref(fc), self.stream()), "dvm_tune")
+        return bool(fc.value)
+
+    def save(self, path, net=None):
+        """checkpoint: leaf list, f, moments, step count (and the network)"""
+        _check(lib().dvm_save(self.h, None if net is None else net.h, os.fsencode(path), self.stream()), "dvm_save")
+
+    def load(self, path, net=None):
+        _check(lib().dvm_load(self.h, None if net is None else net.h, os.fsencode(path), self.stream()), "dvm_load")
 
     def check(self):
         d = Diag()
@@ -382,8 +421,11 @@ class Batch:
     def step(self, n=1):
         _check(lib().dvm_batch_step(self.h, int(n), self.stream()), "dvm_batch_step")
 
-    def tune(self, reps=3):
-        _check(lib().dvm_batch_tune(self.h, int(reps), self.stream()), "dvm_batch_tune")
+    def tune(self, reps=3, cache_path=None):
+        """per-group kernel shapes by timing (dvm_batch_tune); groups found in
+        the tuner cache file take the stored shape"""
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().dvm_batch_tune(self.h, int(reps), cp, self.stream()), "dvm_batch_tune")
 
     def groups(self):
         n = C.c_int32(0)

@@ -1,0 +1,164 @@
+"""Checkpoint/restart and the persisted autotuner through the C interface:
+a run interrupted by dvm_save / dvm_load into a fresh solver continues
+bitwise; a tuned shape written to the cache is found again; a checkpoint of
+another mesh is refused."""
+import numpy as np
+import pytest
+
+from paper_1503_00707_amd import dvm as D
+from paper_1503_00707_amd import inputs as I
+from tests.gpu_common import Case, balanced, gpu_solver
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(scheme=I.SCHEME_UPWIND1):
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)
+    f = balanced(I.random_forest(21, (2, 2, 2), 3, 0.25, bc))
+    return Case(f, 12, 6.0, scheme=scheme, tau_mode=I.TAU_HS, tau=0.02, inflow=(1.0, 0.9, 0.0, 0.1, 1.0),
+                t_wall=1.1, fields="sines", field_args={"seed": 8})
+
+
+def _state(s):
+    import torch
+    torch.cuda.synchronize()
+    return s.f_canonical().cpu().numpy(), s.moments().cpu().numpy(), s.mom.cpu().numpy()
+
+
+@pytest.mark.parametrize("scheme", [I.SCHEME_UPWIND1, I.SCHEME_MUSCL])
+@pytest.mark.parametrize("precision", [D.PREC_FP64, D.PREC_FP32])
+def test_save_load_resumes_bitwise(tmp_path, precision, scheme):
+    case = _case(scheme)
+    dm, a = gpu_solver(case, precision)
+    dt = a.dt(case.cfl)
+    a.step(20, dt=dt)
+    ref = _state(a)
+    _, ref_sums, _, ref_n = a.check()
+    dm2, b = gpu_solver(case, precision)
+    b.step(10, dt=dt)
+    path = str(tmp_path / "state.ckpt")
+    b.save(path)
+    dm3, c = gpu_solver(case, precision)
+    c.step(3, dt=dt)                    # some other state, overwritten by the load
+    c.load(path)
+    c.step(10, dt=dt)
+    got = _state(c)
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    rc, sums, bad, n = c.check()
+    assert rc == 0 and not bad and n == ref_n == 20
+    assert np.array_equal(sums, ref_sums)
+
+
+def test_save_load_hybrid_state_and_network(tmp_path):
+    """a hybrid solver with fluid cells (only their moments are state) and the
+    network with its Adam state round-trip through one checkpoint"""
+    import torch
+    f = balanced(I.random_forest(8, (2, 2, 2), 2, 0.3))
+    case = Case(f, 8, 4.5, tau=0.05, fields="sines", field_args={"seed": 31})
+
+    def hybrid_solver():
+        dm = D.Mesh(case.forest)
+        t = dm.tables()
+        s = D.Solver(dm, D.make_params(8, 4.5, precision=D.PREC_FP64, tau_or_kn=0.05, hybrid=True))
+        s.init_maxwellian(I.fields("sines", I.leaf_centres(case.forest)[t["input"]], seed=31))
+        return dm, s
+
+    rng = np.random.default_rng(5)
+    mask = (rng.random(1 << 12) < 0.5).astype(np.uint8)
+    dm, a = hybrid_solver()
+    dt = a.dt(0.5)
+    a.hybrid_step(mask[:a.n], n=6, dt=dt)
+    ref = (a.mom.cpu().numpy(), a.moments().cpu().numpy())
+    dm2, b = hybrid_solver()
+    b.hybrid_step(mask[:b.n], n=3, dt=dt)
+    p = I.mlp_init(3).astype(np.float32)
+    net = D.MLP(p, max_batch=64)
+    x = torch.as_tensor(rng.normal(0, 1, (64, 10)).astype(np.float32)).cuda()
+    y = torch.as_tensor((rng.random(64) < 0.4).astype(np.float32)).cuda()
+    net.set_normalization(x)
+    for _ in range(3):
+        net.train_step(x, y, lr=1e-2, pos_weight=1.5)
+    path = str(tmp_path / "hyb.ckpt")
+    b.save(path, net)
+    net.train_step(x, y, lr=1e-2, pos_weight=1.5)
+    after4 = net.params.cpu().numpy().copy()
+    dm3, c = hybrid_solver()
+    net2 = D.MLP(I.mlp_init(9).astype(np.float32), max_batch=64)
+    c.load(path, net2)
+    assert not np.array_equal(net2.params.cpu().numpy(), after4)  # saved before the fourth step
+    net2.train_step(x, y, lr=1e-2, pos_weight=1.5)  # Adam state and step count restored too
+    assert np.array_equal(net2.params.cpu().numpy(), after4)
+    with pytest.raises(RuntimeError):
+        c.step(1, dt=dt)                 # fluid cells restored: their f is stale
+    c.hybrid_step(mask[:c.n], n=3, dt=dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.mom.cpu().numpy(), ref[0])
+    assert np.array_equal(c.moments().cpu().numpy(), ref[1])
+
+
+def test_load_refuses_another_mesh(tmp_path):
+    case = _case()
+    dm, a = gpu_solver(case, D.PREC_FP32)
+    path = str(tmp_path / "a.ckpt")
+    a.save(path)
+    other = Case(balanced(I.random_forest(22, (2, 2, 2), 3, 0.25, case.forest.bc)), 12, 6.0,
+                 tau_mode=I.TAU_HS, tau=0.02, fields="sines", field_args={"seed": 8})
+    dm2, b = gpu_solver(other, D.PREC_FP32)
+    with pytest.raises(D.DvmError) as e:
+        b.load(path)
+    assert e.value.code == D.ERR_ARG
+    dm3, c = gpu_solver(case, D.PREC_FP64)   # same mesh, other precision
+    with pytest.raises(D.DvmError):
+        c.load(path)
+    with open(path, "r+b") as fh:              # a damaged payload byte
+        fh.seek(-100, 2)
+        v = fh.read(1)
+        fh.seek(-100, 2)
+        fh.write(bytes([v[0] ^ 0xFF]))
+    dm4, d = gpu_solver(case, D.PREC_FP32)
+    with pytest.raises(D.DvmError):
+        d.load(path)
+
+
+def test_tune_persists_and_reuses_its_choice(tmp_path):
+    """dvm_tune times the shapes once and writes the choice; a second solver
+    of the same kind takes it from the cache; the tuned solver steps as a
+    solver set to that shape by hand, bitwise"""
+    import torch
+    case = _case()
+    path = str(tmp_path / "tune.txt")
+    dm, a = gpu_solver(case, D.PREC_FP32)
+    assert a.tune(path, reps=1) is False
+    shape = a.get_shape()
+    dm2, b = gpu_solver(case, D.PREC_FP32)
+    assert b.tune(path, reps=1) is True
+    assert b.get_shape() == shape
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and " nh=6 fp64=0 scheme=0 | " in lines[0]
+    dm3, c = gpu_solver(case, D.PREC_FP32)
+    c.set_shape(*shape)
+    dt = a.dt(0.5)
+    a.init_maxwellian(np_prim(case, dm))
+    c.init_maxwellian(np_prim(case, dm3))
+    a.step(4, dt=dt)
+    c.step(4, dt=dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.f_canonical().cpu().numpy(), c.f_canonical().cpu().numpy())
+    # the batch tuner writes its groups under their own key and reads them back
+    from tests.test_gpu_batch import _instances, _solver
+    inst = _instances(11, 3, D.PREC_FP32)
+    sides = [_solver(w, f, D.PREC_FP32) for w, f in inst]
+    bt = D.Batch([s for _, s in sides])
+    bt.tune(reps=1, cache_path=path)
+    first = [(g["nh"], g["threads"], g["wpe"], g["xcd_group"], g["nt_store"]) for g in bt.groups()]
+    kinds = [line.split()[0] for line in open(path).read().splitlines()]
+    assert kinds.count("batch") == len(first) and kinds.count("step") == 1
+    bt2 = D.Batch([s for _, s in sides])
+    bt2.tune(reps=1, cache_path=path)
+    assert [(g["nh"], g["threads"], g["wpe"], g["xcd_group"], g["nt_store"]) for g in bt2.groups()] == first
+
+
+def np_prim(case, dm):
+    from tests.gpu_common import prim_for
+    return prim_for(case, dm.tables()["input"])

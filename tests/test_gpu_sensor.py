@@ -175,6 +175,18 @@ def test_hybrid_mixed_mask_matches_oracle_fp64(frac):
     fg = s.f_canonical().cpu().numpy()
     kin = h.kinetic
     assert np.abs(fg[kin] - h.f[kin]).max() <= 1e-12 * np.abs(h.f[kin]).max()
+    # dvm_moments after hybrid steps: kinetic cells from f, fluid cells their U
+    assert (~kin).any() and kin.any()
+    Mg = s.moments().cpu().numpy()
+    assert np.all(np.abs(Mg - h.U).max(axis=1) <= 1e-12 * scale)
+    # the solver's f is stale in fluid cells: plain and batched steps refuse it,
+    # and the moments buffer itself is not a valid output
+    with pytest.raises(RuntimeError):
+        s.step(1, dt=dt)
+    with pytest.raises(RuntimeError):
+        D.Batch([s])
+    rc = D.lib().dvm_moments(s.h, s.mom.data_ptr(), s.stream())
+    assert rc == D.ERR_ARG
 
 
 def test_hybrid_all_fluid_uniform_state_stationary_and_conservative():

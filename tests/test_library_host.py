@@ -198,3 +198,29 @@ def test_split_setting_host_only():
     assert D.lib().dvm_tune_split(h, 1, 100, 31, None) == D.ERR_UNSUPPORTED
     assert D.lib().dvm_tune_split(h, 1, 576, 71, None) == D.OK
     D.lib().dvm_destroy_solver(h)
+
+
+def test_tuner_cache_file_round_trip(tmp_path):
+    """the tuner cache (dvm_tune, dvm_batch_tune) keeps one line per key and
+    returns what was stored; a replaced key keeps one line; other keys and
+    unreadable lines survive; a missing file or key is not found"""
+    path = str(tmp_path / "tune.txt")
+    assert D.tune_cache_get(path, "step", "gfx950", 12, 0, 0) is None
+    D.tune_cache_put(path, "step", "gfx950", 12, 0, 0, (192, 31, 512, 1), 29.5)
+    D.tune_cache_put(path, "batch", "gfx950", 6, 0, 0, (128, 60, 64, 1), 7.25)
+    D.tune_cache_put(path, "step", "gfx950", 12, 1, 0, (576, 30, 64, 1), 85.0)
+    with open(path, "a") as fh:
+        fh.write("not a cache line\n")
+    assert D.tune_cache_get(path, "step", "gfx950", 12, 0, 0) == ((192, 31, 512, 1), 29.5)
+    assert D.tune_cache_get(path, "batch", "gfx950", 6, 0, 0) == ((128, 60, 64, 1), 7.25)
+    assert D.tune_cache_get(path, "step", "gfx950", 12, 1, 0) == ((576, 30, 64, 1), 85.0)
+    assert D.tune_cache_get(path, "step", "gfx942", 12, 0, 0) is None      # another architecture
+    assert D.tune_cache_get(path, "step", "gfx950", 12, 0, 1) is None      # another scheme
+    assert D.tune_cache_get(path, "batch", "gfx950", 12, 0, 0) is None     # another kind
+    D.tune_cache_put(path, "step", "gfx950", 12, 0, 0, (256, 0, 64, 0), 31.0)
+    assert D.tune_cache_get(path, "step", "gfx950", 12, 0, 0) == ((256, 0, 64, 0), 31.0)
+    lines = open(path).read().splitlines()
+    assert sum(line.startswith("step gfx950 nh=12 fp64=0 scheme=0 |") for line in lines) == 1
+    assert "not a cache line" in lines and len(lines) == 4
+    with pytest.raises(D.DvmError):
+        D.tune_cache_put(path, "other", "gfx950", 12, 0, 0, (256, 0, 64, 0), 1.0)
