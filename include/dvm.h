@@ -442,6 +442,25 @@ int dvm_mlp_adam(dvm_mlp *net, float lr, void *stream);
 int dvm_mlp_train_step(dvm_mlp *net, const float *x, const float *y, int64_t n, float lr, float pos_weight,
                        void *stream);
 int dvm_mlp_buffers(const dvm_mlp *net, const float **grads, const double **loss);
+
+/*
+ * dvm_mlp_gradient_noalloc -- for callers that cannot allocate device memory
+ * or bind a workspace (code under HIP graph capture, tight training or
+ * serving loops): the loss and weight gradients of dvm_mlp_gradient, written
+ * to the caller's grad[DVM_MLP_WEIGHTS] (FP32, device) and *loss (FP64,
+ * device), from the parameter block params[DVM_MLP_PARAMS] (device).  No
+ * network object, no workspace: the per-sample scratch lives in a static
+ * device array of the library, one per GPU, sized for
+ * DVM_NOALLOC_MAX_BATCH samples (about 10.4 MiB, held until the process
+ * ends).  n outside [1, DVM_NOALLOC_MAX_BATCH] is DVM_ERR_WORKSPACE.  Same
+ * kernels as dvm_mlp_gradient, so the same result bitwise.  Every call on a
+ * GPU shares that scratch: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.  Calls no
+ * hipMalloc/hipFree.
+ */
+#define DVM_NOALLOC_MAX_BATCH 8192
+int dvm_mlp_gradient_noalloc(const float *params, const float *x, const float *y, int64_t n, float pos_weight,
+                             float *grad, double *loss, void *stream);
 void dvm_destroy_mlp(dvm_mlp *net);
 int dvm_sensor(dvm_solver *s, const dvm_mlp *net, double kappa, uint8_t *mask, float *score, void *stream);
 int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double dt, double cfl, void *stream);

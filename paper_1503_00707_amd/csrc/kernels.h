@@ -112,6 +112,10 @@ hipError_t launch_train(const float *params, const float *x, const float *y, int
                         float *rec, double *loss_part, float *grad, double *loss, hipStream_t st);
 hipError_t launch_adam(float *params, float *m, float *v, const float *grad, float lr, float c1, float c2,
                        hipStream_t st);
+// launch_train with its scratch in a static device array (no allocation)
+constexpr int64_t kNoAllocMaxBatch = 8192;
+hipError_t launch_train_noalloc(const float *params, const float *x, const float *y, int64_t n, float pos_weight,
+                                float *grad, double *loss, hipStream_t st);
 hipError_t launch_norm_stats(const float *x, int64_t n, float *params, hipStream_t st);
 hipError_t launch_mask_eff(const uint8_t *in, uint8_t *out, const DevCell *cells, int64_t n, hipStream_t st);
 hipError_t launch_hybrid(bool fp64, const StepArgs &a, const HybArgsPub &h, hipStream_t st);

@@ -9,6 +9,8 @@
 
 using namespace dvm;
 
+static_assert(DVM_NOALLOC_MAX_BATCH == kNoAllocMaxBatch, "static scratch limit");
+
 namespace {
 
 SensorArgsPub sensor_args(const dvm_solver *s) {
@@ -125,6 +127,17 @@ int dvm_mlp_gradient(dvm_mlp *net, const float *x, const float *y, int64_t n, fl
     hipError_t e = launch_train(net->params, x, y, n, pos_weight, net->rec(), net->lpart(), net->grad(), net->loss(),
                                 S(stream));
     return e == hipSuccess ? DVM_OK : hip_fail(e, "gradient");
+}
+
+int dvm_mlp_gradient_noalloc(const float *params, const float *x, const float *y, int64_t n, float pos_weight,
+                             float *grad, double *loss, void *stream) {
+    clear_error();
+    if (!params || !x || !y || !grad || !loss || !(pos_weight > 0)) return fail(DVM_ERR_ARG, "bad argument");
+    if (n < 1 || n > kNoAllocMaxBatch)
+        return fail(DVM_ERR_WORKSPACE, "batch of %lld samples outside [1, %lld], the static scratch's limit",
+                    (long long)n, (long long)kNoAllocMaxBatch);
+    hipError_t e = launch_train_noalloc(params, x, y, n, pos_weight, grad, loss, S(stream));
+    return e == hipSuccess ? DVM_OK : hip_fail(e, "gradient (static scratch)");
 }
 
 int dvm_mlp_adam(dvm_mlp *net, float lr, void *stream) {

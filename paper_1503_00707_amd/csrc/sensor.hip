@@ -2,9 +2,41 @@
 // (sensor_impl.h), both storage precisions.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sensor_impl.h"
 
 namespace dvm {
+
+// Static scratch of dvm_mlp_gradient_noalloc: the per-sample records and the
+// per-block loss partials of up to kNoAllocMaxBatch samples.  Each GPU holds
+// its own copy until the process ends; every call on a GPU shares it.
+namespace {
+constexpr size_t kScratchRec = (size_t(kNoAllocMaxBatch) * kMlpRecord * sizeof(float) + 255) & ~size_t(255);
+constexpr size_t kScratchPart = (size_t((kNoAllocMaxBatch + 255) / 256) * sizeof(double) + 255) & ~size_t(255);
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) char scratch[kScratchRec + kScratchPart];
+
+// Device address of this GPU's scratch (the host-side name of the array is
+// not a device address): looked up once per device, with it current.
+static hipError_t scratch_on_device(char **out) {
+    static std::mutex mu;
+    static char *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<char *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 static_assert(sizeof(SensorArgsPub) == sizeof(impl::FeatArgs), "argument layout");
 static_assert(sizeof(HybArgsPub) == sizeof(impl::HybArgs), "argument layout");
@@ -51,6 +83,18 @@ hipError_t launch_train(const float *params, const float *x, const float *y, int
     hipLaunchKernelGGL(impl::k_train_grads, dim3(unsigned((impl::kWeights + 255) / 256)), dim3(256), 0, st, rec, n,
                        loss_part, int(nb), grad, loss);
     return hipGetLastError();
+}
+
+hipError_t launch_train_noalloc(const float *params, const float *x, const float *y, int64_t n, float pos_weight,
+                                float *grad, double *loss, hipStream_t st) {
+    if (n < 1 || n > kNoAllocMaxBatch) return hipErrorInvalidValue;
+    char *base = nullptr;
+    hipError_t e = scratch_on_device(&base);
+    if (e != hipSuccess) return e;
+    // every record and partial the gradient kernel reads is written first by
+    // the forward/backward kernel of the same call: nothing to clear
+    return launch_train(params, x, y, n, pos_weight, reinterpret_cast<float *>(base),
+                        reinterpret_cast<double *>(base + kScratchRec), grad, loss, st);
 }
 
 hipError_t launch_adam(float *params, float *m, float *v, const float *grad, float lr, float c1, float c2,

@@ -33,6 +33,7 @@ EXPORTED = [
     "dvm_mlp_set_normalization", "dvm_mlp_forward", "dvm_mlp_gradient", "dvm_mlp_adam", "dvm_mlp_train_step",
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
     "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
+    "dvm_mlp_gradient_noalloc",
 ]
 MLP_WEIGHTS, MLP_PARAMS = 4929, 4949
 
@@ -114,6 +115,7 @@ def lib():
         L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
         L.dvm_save.argtypes = [P, P, C.c_char_p, P]
         L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_mlp_gradient_noalloc.argtypes = [P, P, P, C.c_int64, C.c_float, P, P, P]
         L.dvm_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, C.c_int32, C.c_int32, C.c_int32, P,
                                          C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.dvm_tune_cache_put.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, C.c_int32, C.c_int32, C.c_int32, P,
@@ -449,6 +451,24 @@ class Batch:
                 self.h = None
         except Exception:
             pass
+
+
+def mlp_gradient_noalloc(params, x, y, pos_weight=1.0, grad=None, loss=None):
+    """loss and weight gradients of the network with the library's static
+    scratch (dvm_mlp_gradient_noalloc): no network object, no workspace.
+    params, x, y, grad (float32 [MLP_WEIGHTS]) and loss (float64 [1]) are
+    CUDA tensors; returns (grad, loss)."""
+    import torch
+    x, y = x.contiguous(), y.contiguous()
+    if grad is None:
+        grad = torch.empty(MLP_WEIGHTS, dtype=torch.float32, device="cuda")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(lib().dvm_mlp_gradient_noalloc(params.data_ptr(), x.data_ptr(), y.data_ptr(), x.shape[0],
+                                          float(pos_weight), grad.data_ptr(), loss.data_ptr(),
+                                          C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "dvm_mlp_gradient_noalloc")
+    return grad, loss
 
 
 class MLP:
