@@ -20,6 +20,9 @@
  *                Maxwellian corrected by the polynomial P of eq. (6) so that
  *                mass, momentum and energy are conserved (section 3.2); the
  *                5x5 system is solved by Gauss elimination (section 3.2).
+ *                Or the Boltzmann collision integral of hard spheres on
+ *                Korobov lattice nodes, eqs. (3)-(6) of section 3.2, with the
+ *                same conservative correction (see or_korobov_tables()).
  *
  * Everything is FP64.  f is stored cell-major in canonical velocity order
  * i = (kx*Ny + ky)*Nz + kz, cells in Morton order.  OpenMP parallelises the
@@ -595,7 +598,18 @@ typedef struct {
     double tau_or_kn;
     double inflow[5]; /* rho, ux, uy, uz, T of the inflow Maxwellian */
     double t_wall;    /* temperature of the diffuse wall (wall at rest) */
+    int64_t korobov_p; /* collision 3: lattice points per velocity node (prime) */
+    int64_t korobov_a; /* collision 3: lattice generator (0: the optimal one) */
 } or_params;
+
+/* Korobov tables of one velocity grid: per node i and trial k, the partner
+ * node j and the nodes l, m of the two post-collision velocities (-1 when a
+ * velocity leaves the grid), and the weight W = V_box |g| / p; [i][k]. */
+typedef struct {
+    int64_t p, a, nv;
+    int32_t *j, *l, *m;
+    double *W;
+} or_korobov;
 
 typedef struct {
     const or_mesh *m;
@@ -616,7 +630,185 @@ typedef struct {
     int64_t *cells;      /* row -> cell */
     int64_t *row;        /* cell -> row, -1 when not held */
     uint8_t *valid, *valid_n, *sig_ok;
+    or_korobov *kt;      /* collision 3 */
 } or_solver;
+
+/* ------------------------------------------------------------------------ */
+/* Boltzmann collision integral on Korobov nodes (section 3.2, eqs. 3-6)     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper gives the structure of the discrete collision integral (eqs. 3-5:
+ * per velocity node i a fixed list of M(i) trials, each with a partner node
+ * gamma and a pair of nodes l, m, and weights b, c shared by all cells), not
+ * the tables.  Reading used here (hard spheres of unit total cross section,
+ * non-dimensional units of eq. 1):
+ *   I(f)(xi) = int dxi* int dOmega/(4 pi) |g| (f(xi') f(xi*') - f(xi) f(xi*)),
+ *   g = xi* - xi,  xi' = c + (|g|/2) n,  xi*' = c - (|g|/2) n,  c = (xi + xi*)/2,
+ *   df/dt = I(f) / Kn.
+ * For node i the 5-dimensional integral over the partner velocity (the
+ * velocity box) and the direction n is a p-point Korobov lattice rule
+ * (rank 1, generator a, p prime):
+ *   z_d(k) = k a^d mod p,  d = 0..4, k = 0..p-1,
+ *   shifted per node:  q_d = (z_d(k) + s_d(i)) mod p,  s_d(i) = (i + 1) c_d mod p,
+ *                      c_d = (2654435761 mod p) (d + 1) mod p,
+ *   x_d = (q_d + 1/2) / p,
+ *   partner node j_b = floor(x_b N_b) = ((2 q_b + 1) N_b) div (2 p), b = 0, 1, 2,
+ *   direction cos(theta) = 1 - 2 x_3, phi = 2 pi x_4,
+ * the post-collision velocities belong to the nodes whose velocity cells hold
+ * them (l, m; a trial whose xi' or xi*' leaves the grid contributes no gain),
+ * and every trial weighs W = V_box |g| / p (the box volume over p, times the
+ * relative speed; the sphere average cancels the 1/(4 pi)):
+ *   B_i = sum_k W f_j          (eq. 4, the collision frequency)
+ *   C_i = sum_k W f_l f_m      (eq. 5, the inverse-collision integral)
+ *   I_i = -f_i P_i B_i + C_i   (eq. 6),  P_i = 1 + d0 + dx xi_x + dy xi_y + dz xi_z + d2 |xi|^2,
+ * the five d from sum_i w psi_a I_i = 0, psi = (1, xi, |xi|^2) (conservation of
+ * mass, momentum and energy), by Gauss elimination.  Time step (after the
+ * transport): f' = f* + (dt / Kn) I(f*).
+ * The generator is Korobov's optimal coefficient for the P_2 criterion:
+ *   P_2(a) = -1 + (1/p) sum_k prod_d (1 + 2 pi^2 B_2(z_d(k) / p)),  B_2(x) = x^2 - x + 1/6,
+ * the first a in 2, 3, ..., p - 1 with the smallest value (values within 1e-9
+ * relative of each other count as equal).
+ */
+static int is_prime64(int64_t p) {
+    if (p < 2) return 0;
+    for (int64_t q = 2; q * q <= p; ++q)
+        if (p % q == 0) return 0;
+    return 1;
+}
+
+static double korobov_p2(int64_t p, int64_t a) {
+    double sum = 0.0;
+    for (int64_t k = 0; k < p; ++k) {
+        double prod = 1.0;
+        int64_t z = k;
+        for (int d = 0; d < 5; ++d) {
+            double x = (double)z / (double)p;
+            prod *= 1.0 + 2.0 * M_PI * M_PI * (x * x - x + 1.0 / 6.0);
+            z = (z * a) % p;
+        }
+        sum += prod;
+    }
+    return -1.0 + sum / (double)p;
+}
+
+/* Korobov's optimal generator for a p-point lattice in 5 dimensions, or -1 */
+int64_t or_korobov_generator(int64_t p) {
+    if (!is_prime64(p) || p < 5 || p >= (1ll << 31)) return -1;
+    int64_t best = -1;
+    double best_v = 0.0;
+    for (int64_t a = 2; a < p; ++a) {
+        double v = korobov_p2(p, a);
+        /* a, -a, 1/a and -1/a (mod p) give the same lattice up to the order and
+         * sign of the coordinates, hence the same value: values within 1e-9
+         * relative are ties, and the first a wins */
+        if (best < 0 || v < best_v - 1e-9 * fabs(best_v)) { best = a; best_v = v; }
+    }
+    return best;
+}
+
+/* node index of velocity component v along axis b, -1 outside the grid */
+static int node_of(const or_vgrid *g, int b, double v) {
+    double t = floor((v - g->lo[b]) / g->d[b]);
+    if (t < 0.0 || t >= (double)g->n[b]) return -1;
+    return (int)t;
+}
+
+static void korobov_free(or_korobov *t) {
+    if (!t) return;
+    free(t->j); free(t->l); free(t->m); free(t->W); free(t);
+}
+
+static or_korobov *korobov_build(const or_vgrid *g, int64_t p, int64_t a) {
+    if (!is_prime64(p) || p < 5 || p >= (1ll << 31) || a < 1 || a >= p) return NULL;
+    or_korobov *t = (or_korobov *)calloc(1, sizeof(or_korobov));
+    int64_t nv = g->nv;
+    t->p = p; t->a = a; t->nv = nv;
+    t->j = (int32_t *)malloc((size_t)(nv * p) * sizeof(int32_t));
+    t->l = (int32_t *)malloc((size_t)(nv * p) * sizeof(int32_t));
+    t->m = (int32_t *)malloc((size_t)(nv * p) * sizeof(int32_t));
+    t->W = (double *)malloc((size_t)(nv * p) * sizeof(double));
+    double vbox = (g->hi[0] - g->lo[0]) * (g->hi[1] - g->lo[1]) * (g->hi[2] - g->lo[2]);
+    int64_t apow[5], c[5];
+    apow[0] = 1;
+    for (int d = 1; d < 5; ++d) apow[d] = (apow[d - 1] * a) % p;
+    for (int d = 0; d < 5; ++d) c[d] = ((2654435761ll % p) * (d + 1)) % p;
+    for (int64_t i = 0; i < nv; ++i) {
+        double xi[3];
+        vgrid_xi(g, i, xi);
+        int64_t sft[5];
+        for (int d = 0; d < 5; ++d) sft[d] = ((i + 1) % p) * c[d] % p;
+        for (int64_t k = 0; k < p; ++k) {
+            int64_t q[5];
+            for (int d = 0; d < 5; ++d) q[d] = ((k * apow[d]) % p + sft[d]) % p;
+            int jb[3];
+            for (int b = 0; b < 3; ++b) jb[b] = (int)(((2 * q[b] + 1) * g->n[b]) / (2 * p));
+            int64_t j = ((int64_t)jb[0] * g->n[1] + jb[1]) * g->n[2] + jb[2];
+            double xs[3] = {g->xi[0][jb[0]], g->xi[1][jb[1]], g->xi[2][jb[2]]};
+            double gx = xs[0] - xi[0], gy = xs[1] - xi[1], gz = xs[2] - xi[2];
+            double gg = sqrt(gx * gx + gy * gy + gz * gz);
+            double x3 = ((double)q[3] + 0.5) / (double)p, x4 = ((double)q[4] + 0.5) / (double)p;
+            double ct = 1.0 - 2.0 * x3;
+            double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+            double ph = 2.0 * M_PI * x4;
+            double n[3] = {st * cos(ph), st * sin(ph), ct};
+            int l1[3], l2[3], ok = 1;
+            for (int b = 0; b < 3; ++b) {
+                double cb = 0.5 * (xi[b] + xs[b]);
+                l1[b] = node_of(g, b, cb + 0.5 * gg * n[b]);
+                l2[b] = node_of(g, b, cb - 0.5 * gg * n[b]);
+                if (l1[b] < 0 || l2[b] < 0) ok = 0;
+            }
+            int64_t e = i * p + k;
+            t->j[e] = (int32_t)j;
+            t->l[e] = ok ? (int32_t)(((int64_t)l1[0] * g->n[1] + l1[1]) * g->n[2] + l1[2]) : -1;
+            t->m[e] = ok ? (int32_t)(((int64_t)l2[0] * g->n[1] + l2[1]) * g->n[2] + l2[2]) : -1;
+            t->W[e] = vbox * gg / (double)p;
+        }
+    }
+    return t;
+}
+
+/* B (eq. 4) and C (eq. 5) of one cell's distribution */
+static void korobov_terms(const or_korobov *t, const double *f, double *B, double *C) {
+    for (int64_t i = 0; i < t->nv; ++i) {
+        double b = 0.0, c = 0.0;
+        for (int64_t k = 0; k < t->p; ++k) {
+            int64_t e = i * t->p + k;
+            b += t->W[e] * f[t->j[e]];
+            if (t->l[e] >= 0) c += t->W[e] * f[t->l[e]] * f[t->m[e]];
+        }
+        B[i] = b;
+        C[i] = c;
+    }
+}
+
+/* I of eq. (6): the conservatively corrected collision integral of one cell */
+static int korobov_integral(const or_vgrid *g, const or_korobov *t, const double *f, double *I, double *B, double *C) {
+    korobov_terms(t, f, B, C);
+    double G[25], r[5], d[5];
+    memset(G, 0, sizeof G);
+    memset(r, 0, sizeof r);
+    for (int64_t i = 0; i < g->nv; ++i) {
+        double xi[3];
+        vgrid_xi(g, i, xi);
+        double psi[5] = {1.0, xi[0], xi[1], xi[2], xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]};
+        double fb = f[i] * B[i];
+        for (int a = 0; a < 5; ++a) {
+            r[a] += g->w * psi[a] * (C[i] - fb);
+            for (int b = 0; b < 5; ++b) G[a * 5 + b] += g->w * psi[a] * psi[b] * fb;
+        }
+    }
+    int rc = gauss_solve(5, G, r, d);
+    if (rc) return rc;
+    for (int64_t i = 0; i < g->nv; ++i) {
+        double xi[3];
+        vgrid_xi(g, i, xi);
+        double P = 1.0 + d[0] + d[1] * xi[0] + d[2] * xi[1] + d[3] * xi[2] +
+                   d[4] * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
+        I[i] = -f[i] * P * B[i] + C[i];
+    }
+    return OR_OK;
+}
 
 static int64_t row_of(const or_solver *s, int64_t c) { return s->row ? s->row[c] : c; }
 static int64_t cell_of(const or_solver *s, int64_t r) { return s->cells ? s->cells[r] : r; }
@@ -635,6 +827,7 @@ void or_solver_free(or_solver *s) {
     if (!s) return;
     free(s->f); free(s->fn); free(s->ghost_in); free(s->wall_m1); free(s->sigma);
     free(s->cells); free(s->row); free(s->valid); free(s->valid_n); free(s->sig_ok);
+    korobov_free(s->kt);
     vgrid_free(&s->g);
     free(s);
 }
@@ -688,6 +881,11 @@ int or_solver_new_subset(const or_mesh *m, const or_params *p, int64_t n_sub, co
     if (!rc && has_wall) {
         rc = target_of_prim(pw, tgt);
         if (!rc) rc = corrected_maxwellian(&s->g, tgt, s->wall_m1);
+    }
+    if (!rc && p->collision == 3) {
+        int64_t a = p->korobov_a ? p->korobov_a : or_korobov_generator(p->korobov_p);
+        s->kt = korobov_build(&s->g, p->korobov_p, a);
+        if (!s->kt || !(p->tau_or_kn > 0.0)) rc = OR_ERR_ARG;
     }
     if (rc) { or_solver_free(s); return rc; }
     *out = s;
@@ -911,13 +1109,21 @@ static double relaxation_time(const or_params *p, double rho, double T) {
  *   EULER: f' = f* + dt/tau (Mt - f*)
  *   OFF:   f' = f*
  */
-static int collide_cell(const or_vgrid *g, const or_params *p, double dt, const double *fs, double *out, double *work) {
+static int collide_cell(const or_vgrid *g, const or_params *p, const or_korobov *kt, double dt, const double *fs,
+                        double *out, double *work) {
     int64_t nv = g->nv;
     if (p->collision == 2) { memcpy(out, fs, (size_t)nv * sizeof(double)); return OR_OK; }
     double mom[5], rho, u[3], T;
     moments_of(g, fs, mom);
     int rc = primitive_of(mom, &rho, u, &T);
     if (rc) { memcpy(out, fs, (size_t)nv * sizeof(double)); return rc; }
+    if (p->collision == 3) { /* Boltzmann integral on Korobov nodes, explicit Euler */
+        double *I = work, *B = work + nv, *C = work + 2 * nv;
+        rc = korobov_integral(g, kt, fs, I, B, C);
+        if (rc) { memcpy(out, fs, (size_t)nv * sizeof(double)); return rc; }
+        for (int64_t v = 0; v < nv; ++v) out[v] = fs[v] + dt / p->tau_or_kn * I[v];
+        return OR_OK;
+    }
     rc = corrected_maxwellian(g, mom, work);
     if (rc) { memcpy(out, fs, (size_t)nv * sizeof(double)); return rc; }
     double tau = relaxation_time(p, rho, T);
@@ -938,14 +1144,14 @@ int or_step(or_solver *s, double dt, int n_steps) {
         int err = 0;
 #pragma omp parallel reduction(| : err)
         {
-            double *work = (double *)malloc((size_t)nv * sizeof(double));
+            double *work = (double *)malloc((size_t)(3 * nv) * sizeof(double));
 #pragma omp for schedule(dynamic, 16)
             for (int64_t r = 0; r < n; ++r) {
                 if (s->valid && !s->valid[r]) { /* not exact any more: carried, not collided */
                     memcpy(s->f + r * nv, s->fn + r * nv, (size_t)nv * sizeof(double));
                     continue;
                 }
-                if (collide_cell(&s->g, &s->p, dt, s->fn + r * nv, s->f + r * nv, work)) err |= 1;
+                if (collide_cell(&s->g, &s->p, s->kt, dt, s->fn + r * nv, s->f + r * nv, work)) err |= 1;
             }
             free(work);
         }
@@ -1020,9 +1226,46 @@ int or_cell_moments(const int nvx[3], const double lo[3], const double hi[3], co
 int or_cell_collide(const or_params *p, double dt, const double *fs, double *out) {
     or_vgrid g;
     vgrid_init(&g, p->nv, p->vlo, p->vhi);
-    double *work = (double *)malloc((size_t)g.nv * sizeof(double));
-    int rc = collide_cell(&g, p, dt, fs, out, work);
+    or_korobov *kt = NULL;
+    if (p->collision == 3) {
+        int64_t a = p->korobov_a ? p->korobov_a : or_korobov_generator(p->korobov_p);
+        kt = korobov_build(&g, p->korobov_p, a);
+        if (!kt) { vgrid_free(&g); return OR_ERR_ARG; }
+    }
+    double *work = (double *)malloc((size_t)(3 * g.nv) * sizeof(double));
+    int rc = collide_cell(&g, p, kt, dt, fs, out, work);
     free(work);
+    korobov_free(kt);
+    vgrid_free(&g);
+    return rc;
+}
+
+/* Korobov tables of a velocity grid ([nv][p] each; any output may be NULL) */
+int or_korobov_tables(const int nvx[3], const double lo[3], const double hi[3], int64_t p, int64_t a, int32_t *j,
+                      int32_t *l, int32_t *m, double *W) {
+    or_vgrid g;
+    vgrid_init(&g, nvx, lo, hi);
+    or_korobov *t = korobov_build(&g, p, a);
+    vgrid_free(&g);
+    if (!t) return OR_ERR_ARG;
+    size_t n = (size_t)(t->nv * p);
+    if (j) memcpy(j, t->j, n * sizeof(int32_t));
+    if (l) memcpy(l, t->l, n * sizeof(int32_t));
+    if (m) memcpy(m, t->m, n * sizeof(int32_t));
+    if (W) memcpy(W, t->W, n * sizeof(double));
+    korobov_free(t);
+    return OR_OK;
+}
+
+/* one cell: B (eq. 4), C (eq. 5) and the corrected integral I (eq. 6) */
+int or_korobov_cell(const int nvx[3], const double lo[3], const double hi[3], int64_t p, int64_t a, const double *f,
+                    double *I, double *B, double *C) {
+    or_vgrid g;
+    vgrid_init(&g, nvx, lo, hi);
+    or_korobov *t = korobov_build(&g, p, a);
+    int rc = OR_ERR_ARG;
+    if (t) rc = korobov_integral(&g, t, f, I, B, C);
+    korobov_free(t);
     vgrid_free(&g);
     return rc;
 }

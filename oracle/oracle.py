@@ -22,7 +22,8 @@ FACE_SAME, FACE_COARSER, FACE_FINER, FACE_INFLOW, FACE_OUTFLOW, FACE_WALL = rang
 class OrParams(C.Structure):
     _fields_ = [("nv", C.c_int * 3), ("vlo", C.c_double * 3), ("vhi", C.c_double * 3),
                 ("scheme", C.c_int), ("collision", C.c_int), ("tau_mode", C.c_int),
-                ("tau_or_kn", C.c_double), ("inflow", C.c_double * 5), ("t_wall", C.c_double)]
+                ("tau_or_kn", C.c_double), ("inflow", C.c_double * 5), ("t_wall", C.c_double),
+                ("korobov_p", C.c_int64), ("korobov_a", C.c_int64)]
 
 
 def lib():
@@ -68,6 +69,10 @@ def lib():
         L.or_cell_maxwellian.argtypes = [i32p, f64p, f64p, f64p, f64p]
         L.or_cell_moments.argtypes = [i32p, f64p, f64p, f64p, f64p]
         L.or_cell_collide.argtypes = [C.POINTER(OrParams), C.c_double, f64p, f64p]
+        L.or_korobov_generator.argtypes = [C.c_int64]
+        L.or_korobov_generator.restype = C.c_int64
+        L.or_korobov_tables.argtypes = [i32p, f64p, f64p, C.c_int64, C.c_int64, P, P, P, P]
+        L.or_korobov_cell.argtypes = [i32p, f64p, f64p, C.c_int64, C.c_int64, f64p, f64p, f64p, f64p]
         L.or_set_threads.argtypes = [C.c_int]
         L.or_get_threads.restype = C.c_int
         _LIB = L
@@ -159,7 +164,7 @@ class Mesh:
 
 
 def make_params(nv, vlo, vhi, scheme=0, collision=0, tau_mode=0, tau_or_kn=0.1,
-                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0) -> OrParams:
+                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, korobov_p=0, korobov_a=0) -> OrParams:
     p = OrParams()
     for a in range(3):
         p.nv[a] = int(nv[a])
@@ -170,6 +175,7 @@ def make_params(nv, vlo, vhi, scheme=0, collision=0, tau_mode=0, tau_or_kn=0.1,
     for a in range(5):
         p.inflow[a] = float(inflow[a])
     p.t_wall = float(t_wall)
+    p.korobov_p, p.korobov_a = int(korobov_p), int(korobov_a)
     return p
 
 
@@ -240,6 +246,36 @@ class Solver:
         if getattr(self, "h", None):
             lib().or_solver_free(self.h)
             self.h = None
+
+
+def korobov_generator(p):
+    """Korobov's optimal 5-dimensional generator for a p-point lattice (P_2 criterion)"""
+    return int(lib().or_korobov_generator(int(p)))
+
+
+def korobov_tables(nv, vlo, vhi, p, a):
+    """(j, l, m, W), each [N^3, p]: partner node, post-collision nodes (-1: off the grid), weight"""
+    n = int(np.prod(nv)) * int(p)
+    j, l, m = (np.zeros(n, np.int32) for _ in range(3))
+    W = np.zeros(n)
+    rc = lib().or_korobov_tables(np.asarray(nv, np.int32), np.asarray(vlo, np.float64), np.asarray(vhi, np.float64),
+                                 int(p), int(a), j.ctypes.data, l.ctypes.data, m.ctypes.data, W.ctypes.data)
+    if rc:
+        raise RuntimeError(f"or_korobov_tables: {rc}")
+    sh = (int(np.prod(nv)), int(p))
+    return j.reshape(sh), l.reshape(sh), m.reshape(sh), W.reshape(sh)
+
+
+def korobov_cell(nv, vlo, vhi, p, a, f):
+    """(I, B, C) of one cell: eq. (6), (4), (5)"""
+    n = int(np.prod(nv))
+    f = np.ascontiguousarray(f, np.float64)
+    I, B, Cc = np.zeros(n), np.zeros(n), np.zeros(n)
+    rc = lib().or_korobov_cell(np.asarray(nv, np.int32), np.asarray(vlo, np.float64), np.asarray(vhi, np.float64),
+                               int(p), int(a), f, I, B, Cc)
+    if rc:
+        raise RuntimeError(f"or_korobov_cell: {rc}")
+    return I, B, Cc
 
 
 def cell_maxwellian(nv, vlo, vhi, prim):
