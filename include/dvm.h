@@ -80,6 +80,9 @@ extern "C" {
 #define DVM_COLL_EXP 0          /* f' = Mt + (f* - Mt) exp(-dt/tau) */
 #define DVM_COLL_EULER 1        /* f' = f* + dt/tau (Mt - f*) */
 #define DVM_COLL_OFF 2          /* f' = f* */
+#define DVM_COLL_KOROBOV 3      /* f' = f* + dt/Kn I(f*), I the hard-sphere Boltzmann integral on
+                                   Korobov lattice nodes with the correction of eq. (6)
+                                   (section 3.2); Kn = tau_or_kn; N = 4, 8 or 12 */
 #define DVM_TAU_CONST 0         /* tau = tau_or_kn */
 #define DVM_TAU_HS 1            /* tau = Kn T^(-1/2) / rho (hard sphere) */
 
@@ -118,6 +121,8 @@ typedef struct {
     double t_wall;            /* diffuse-wall temperature */
     int32_t check_every;      /* global sums every k steps (0: never) */
     int32_t hybrid;           /* 1: workspace for dvm_hybrid_step (masks, flux sums) */
+    int32_t korobov_p;        /* DVM_COLL_KOROBOV: lattice points per velocity node (a prime) */
+    int32_t korobov_a;        /* DVM_COLL_KOROBOV: lattice generator; 0: Korobov's optimal one */
 } dvm_params;
 
 typedef struct {
@@ -135,6 +140,27 @@ typedef struct {
     int32_t nonphysical;      /* 1 if the device flag was raised */
     int64_t steps;            /* steps taken since dvm_bind */
 } dvm_diag;
+
+/*
+ * Boltzmann collision integral on Korobov lattice nodes (DVM_COLL_KOROBOV,
+ * section 3.2, eqs. 3-6).  The tables of eqs. 3-5 (per velocity node i and
+ * trial k: the partner node j and the post-collision nodes l, m) are built
+ * on the host when the solver is created and live in its workspace.  For
+ * node i and trial k of a p-point rank-1 lattice in 5 dimensions (generator
+ * a): q_d = (k a^d + (i + 1) c_d) mod p, c_d = (2654435761 mod p)(d + 1) mod p;
+ * j_b = floor((q_b + 1/2) N / p) (b = 0..2); n from cos(theta) = 1 - 2 (q_3 +
+ * 1/2)/p, phi = 2 pi (q_4 + 1/2)/p; l, m the nodes whose velocity cells hold
+ * (xi_i + xi_j)/2 +- |xi_j - xi_i|/2 n (-1: no gain term); weight
+ * V_box |xi_j - xi_i| / p.  Canonical velocity indices; node velocities
+ * -vmax + (k + 1/2) 2 vmax / N.
+ * dvm_korobov_generator -- Korobov's optimal generator of a p-point lattice
+ * in 5 dimensions (smallest P_2 merit, first of ties); DVM_ERR_ARG unless p is
+ * a prime in [5, 2^31).
+ * dvm_korobov_tables -- the tables [N^3][p] of the velocity grid N^3 on
+ * [-vmax, vmax]^3 (host arrays), for tests and inspection.
+ */
+int dvm_korobov_generator(int64_t p, int64_t *a);
+int dvm_korobov_tables(int32_t nv, double vmax, int64_t p, int64_t a, int32_t *j, int32_t *l, int32_t *m);
 
 /* Text of the last error on this thread ("" if none). */
 const char *dvm_last_error(void);

@@ -150,6 +150,7 @@ int dvm_batch_create(dvm_solver *const *solvers, int32_t n, double cfl, dvm_batc
         if (!s) return fail(DVM_ERR_ARG, "solver %d is NULL", i);
         if (s->fp64 != solvers[0]->fp64) return fail(DVM_ERR_UNSUPPORTED, "a batch has one storage precision");
         if (s->muscl) return fail(DVM_ERR_UNSUPPORTED, "batched steps are first order");
+        if (s->korobov()) return fail(DVM_ERR_UNSUPPORTED, "batched steps relax with BGK");
         if (s->hybrid_fluid)
             return fail(DVM_ERR_UNSUPPORTED, "solver %d holds fluid cells from hybrid steps (their f is stale)", i);
         if (uint64_t(s->n) >= (uint64_t(1) << 31)) return fail(DVM_ERR_UNSUPPORTED, "instance too large");

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -120,6 +121,26 @@ hipError_t launch_norm_stats(const float *x, int64_t n, float *params, hipStream
 hipError_t launch_mask_eff(const uint8_t *in, uint8_t *out, const DevCell *cells, int64_t n, hipStream_t st);
 hipError_t launch_hybrid(bool fp64, const StepArgs &a, const HybArgsPub &h, hipStream_t st);
 hipError_t launch_fluid_moments(const uint8_t *mask, const double *mom, double *out, int64_t n, hipStream_t st);
+
+// Boltzmann collision integral on Korobov nodes (korobov.hip / korobov.cpp).
+struct KorArgs {
+    void *f;                 // [n_cells][NV] post-transport state, updated in place
+    const uint64_t *table;   // [p][NV] entries j | l << 16 | m << 32 (internal indices; 0xFFFF: no gain)
+    int64_t n_cells;
+    int p;
+    double w0;               // V_box / p
+    double dt_kn;            // dt / Kn
+    double vmax;             // half width of the velocity grid (basis scale)
+    VelGrid g;
+    int *flag;               // raised if a conservation system is singular
+};
+hipError_t launch_korobov(bool fp64, const KorArgs &a, hipStream_t st);
+bool korobov_supported(int nh);
+int64_t korobov_generator(int64_t p);
+void korobov_tables(int n, double vmax, int64_t p, int64_t a, std::vector<int32_t> &J, std::vector<int32_t> &L,
+                    std::vector<int32_t> &M);
+void korobov_device_table(int nh, const std::vector<int32_t> &J, const std::vector<int32_t> &L,
+                          const std::vector<int32_t> &M, int64_t p, std::vector<uint64_t> &out);
 
 // Deferred-collision engine (lazy_impl.h).
 struct UnitArgsPub {

@@ -86,7 +86,8 @@ StepArgs dvm::solver_step_args(const dvm_solver *s, double dt) {
     a.dt = dt;
     a.h0 = s->m->h0;
     a.g = s->g;
-    a.collision = s->p.collision;
+    // the Korobov collision runs as its own kernel after a transport-only step
+    a.collision = s->korobov() ? DVM_COLL_OFF : s->p.collision;
     a.tau_mode = s->p.tau_mode;
     a.tau_or_kn = s->p.tau_or_kn;
     a.xcd_log2 = 0;
@@ -120,13 +121,24 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         if (!(p->vmax[b] > 0)) return fail(DVM_ERR_ARG, "vmax[%d] must be > 0", b);
     if (p->precision != DVM_PREC_FP64 && p->precision != DVM_PREC_FP32) return fail(DVM_ERR_ARG, "bad precision");
     if (p->scheme != DVM_SCHEME_UPWIND1 && p->scheme != DVM_SCHEME_MUSCL) return fail(DVM_ERR_ARG, "bad scheme");
-    if (p->collision < DVM_COLL_EXP || p->collision > DVM_COLL_OFF) return fail(DVM_ERR_ARG, "bad collision mode");
+    if (p->collision < DVM_COLL_EXP || p->collision > DVM_COLL_KOROBOV) return fail(DVM_ERR_ARG, "bad collision mode");
     if (p->tau_mode != DVM_TAU_CONST && p->tau_mode != DVM_TAU_HS) return fail(DVM_ERR_ARG, "bad tau mode");
     if (p->collision != DVM_COLL_OFF && !(p->tau_or_kn > 0)) return fail(DVM_ERR_ARG, "tau_or_kn must be > 0");
     const bool fp64 = p->precision == DVM_PREC_FP64;
     const int nh = p->nv / 2;
     const int thr = default_threads(fp64, nh);
     if (!thr) return fail(DVM_ERR_UNSUPPORTED, "no device kernel for N = %d (have 4, 8, 12, 16, 24)", p->nv);
+    int64_t kor_a = 0;
+    if (p->collision == DVM_COLL_KOROBOV) {
+        if (!korobov_supported(nh)) return fail(DVM_ERR_UNSUPPORTED, "Korobov collision kernel for N = 4, 8, 12 only");
+        if (p->hybrid) return fail(DVM_ERR_UNSUPPORTED, "the hybrid step relaxes with BGK");
+        if (p->vmax[0] != p->vmax[1] || p->vmax[0] != p->vmax[2])
+            return fail(DVM_ERR_UNSUPPORTED, "Korobov collision on a cubic velocity box only");
+        const int64_t gen = korobov_generator(p->korobov_p);
+        if (gen < 0) return fail(DVM_ERR_ARG, "korobov_p = %d must be a prime in [5, 2^31)", p->korobov_p);
+        kor_a = p->korobov_a ? p->korobov_a : gen;
+        if (kor_a < 1 || kor_a >= p->korobov_p) return fail(DVM_ERR_ARG, "korobov_a must be in [1, p)");
+    }
     dvm_solver *s = new (std::nothrow) dvm_solver();
     if (!s) return fail(DVM_ERR_ARG, "out of host memory");
     s->m = m;
@@ -186,6 +198,15 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->muscl = p->scheme == DVM_SCHEME_MUSCL;
     s->off_face = o;
     if (s->muscl) o += 3 * s->f_bytes;
+    s->off_kor = o;
+    if (p->collision == DVM_COLL_KOROBOV) {
+        s->kor_p = p->korobov_p;
+        s->kor_a = kor_a;
+        std::vector<int32_t> J, L, M;
+        korobov_tables(p->nv, p->vmax[0], s->kor_p, s->kor_a, J, L, M);
+        korobov_device_table(nh, J, L, M, s->kor_p, s->kor_host);
+        o += align256(s->kor_host.size() * sizeof(uint64_t));
+    }
     s->hybrid = p->hybrid != 0;
     s->off_hyb = o;
     if (s->hybrid)
@@ -275,6 +296,11 @@ int dvm_upload(dvm_solver *s, void *stream) {
     }
     e = launch_identity(s->fp64, s->null_rec(), 1, s->nh, st);
     if (e != hipSuccess) return hip_fail(e, "identity record");
+    if (s->korobov()) {
+        e = hipMemcpyAsync(s->ws + s->off_kor, s->kor_host.data(), s->kor_host.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "Korobov table");
+    }
     e = solver_reset_hybrid(s, st);
     if (e != hipSuccess) return hip_fail(e, "hybrid masks");
     s->hybrid_fluid = false;
@@ -377,6 +403,20 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
                 e = launch_step(s->fp64, a, s->cfg, st);
             }
             if (e != hipSuccess) return hip_fail(e, "step");
+            if (s->korobov()) {
+                KorArgs k{};
+                k.f = a.f_out;
+                k.table = s->kor();
+                k.n_cells = s->n;
+                k.p = int(s->kor_p);
+                k.w0 = 8.0 * s->p.vmax[0] * s->p.vmax[0] * s->p.vmax[0] / double(s->kor_p);
+                k.dt_kn = dt / s->p.tau_or_kn;
+                k.vmax = s->p.vmax[0];
+                k.g = s->g;
+                k.flag = s->flag();
+                e = launch_korobov(s->fp64, k, st);
+                if (e != hipSuccess) return hip_fail(e, "Korobov collision");
+            }
             s->lazy_valid = false;
         }
         s->cur ^= 1;
@@ -548,6 +588,7 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous) {
     if (engine < 0) return DVM_OK;  // query only
     if (engine != 0 && engine != 1) return fail(DVM_ERR_ARG, "engine must be 0 (fused) or 1 (deferred collision)");
     if (engine == 1 && s->muscl) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine is first order only");
+    if (engine == 1 && s->korobov()) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine relaxes with BGK");
     if (engine == 1 && size_t(s->n + 1) * size_t(table_stride(s->nh)) * (s->fp64 ? 8 : 4) >= (size_t(1) << 32))
         return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine addresses its records with 32-bit offsets");
     s->engine = engine;

@@ -19,7 +19,7 @@ OK, ERR_ARG, ERR_UNBALANCED, ERR_NOT_PARTITION, ERR_WORKSPACE, ERR_NONPHYSICAL, 
     0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
 SCHEME_UPWIND1, SCHEME_MUSCL = 0, 1
-COLL_EXP, COLL_EULER, COLL_OFF = 0, 1, 2
+COLL_EXP, COLL_EULER, COLL_OFF, COLL_KOROBOV = 0, 1, 2, 3
 TAU_CONST, TAU_HS = 0, 1
 
 EXPORTED = [
@@ -33,7 +33,7 @@ EXPORTED = [
     "dvm_mlp_set_normalization", "dvm_mlp_forward", "dvm_mlp_gradient", "dvm_mlp_adam", "dvm_mlp_train_step",
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
     "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
-    "dvm_mlp_gradient_noalloc",
+    "dvm_mlp_gradient_noalloc", "dvm_korobov_generator", "dvm_korobov_tables",
 ]
 MLP_WEIGHTS, MLP_PARAMS = 4929, 4949
 
@@ -58,7 +58,7 @@ class Params(C.Structure):
     _fields_ = [("nv", C.c_int32), ("vmax", C.c_double * 3), ("precision", C.c_int32), ("scheme", C.c_int32),
                 ("collision", C.c_int32), ("tau_mode", C.c_int32), ("tau_or_kn", C.c_double),
                 ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32),
-                ("hybrid", C.c_int32)]
+                ("hybrid", C.c_int32), ("korobov_p", C.c_int32), ("korobov_a", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -115,6 +115,8 @@ def lib():
         L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
         L.dvm_save.argtypes = [P, P, C.c_char_p, P]
         L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_korobov_generator.argtypes = [C.c_int64, C.POINTER(C.c_int64)]
+        L.dvm_korobov_tables.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, P, P, P]
         L.dvm_mlp_gradient_noalloc.argtypes = [P, P, P, C.c_int64, C.c_float, P, P, P]
         L.dvm_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, C.c_int32, C.c_int32, C.c_int32, P,
                                          C.POINTER(C.c_double), C.POINTER(C.c_int32)]
@@ -211,7 +213,7 @@ class Mesh:
 
 def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=COLL_EXP, tau_mode=TAU_CONST,
                 tau_or_kn=0.1, inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, check_every=0,
-                hybrid=False) -> Params:
+                hybrid=False, korobov_p=0, korobov_a=0) -> Params:
     p = Params()
     p.nv = int(nv)
     vm = (vmax,) * 3 if np.isscalar(vmax) else tuple(vmax)
@@ -224,7 +226,25 @@ def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=
     p.t_wall = float(t_wall)
     p.check_every = int(check_every)
     p.hybrid = int(bool(hybrid))
+    p.korobov_p, p.korobov_a = int(korobov_p), int(korobov_a)
     return p
+
+
+def korobov_generator(p):
+    """Korobov's optimal generator of a p-point lattice in 5 dimensions (dvm_korobov_generator)"""
+    a = C.c_int64(0)
+    _check(lib().dvm_korobov_generator(int(p), C.byref(a)), "dvm_korobov_generator")
+    return a.value
+
+
+def korobov_tables(nv, vmax, p, a):
+    """(j, l, m) [N^3, p] of the Korobov collision tables, canonical velocity order"""
+    n = int(nv) ** 3 * int(p)
+    j, l, m = (np.zeros(n, np.int32) for _ in range(3))
+    _check(lib().dvm_korobov_tables(int(nv), float(vmax), int(p), int(a), j.ctypes.data, l.ctypes.data,
+                                    m.ctypes.data), "dvm_korobov_tables")
+    sh = (int(nv) ** 3, int(p))
+    return j.reshape(sh), l.reshape(sh), m.reshape(sh)
 
 
 def tune_cache_get(path, kind, arch, nh, fp64, scheme):

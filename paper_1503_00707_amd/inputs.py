@@ -22,7 +22,7 @@ import numpy as np
 
 PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
 SCHEME_UPWIND1, SCHEME_MUSCL = 0, 1
-COLL_EXP, COLL_EULER, COLL_OFF = 0, 1, 2
+COLL_EXP, COLL_EULER, COLL_OFF, COLL_KOROBOV = 0, 1, 2, 3
 TAU_CONST, TAU_HS = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 

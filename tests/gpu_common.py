@@ -30,6 +30,7 @@ class Case:
     field_args: dict = dataclasses.field(default_factory=dict)
     solid: object = None
     cfl: float = 0.5
+    korobov_p: int = 0
 
 
 def prim_for(case, input_index):
@@ -42,7 +43,7 @@ def oracle_run(case, steps):
     t = om.tables()
     p = O.make_params((case.nv,) * 3, (-case.vmax,) * 3, (case.vmax,) * 3, scheme=case.scheme,
                       collision=case.collision, tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow,
-                      t_wall=case.t_wall)
+                      t_wall=case.t_wall, korobov_p=case.korobov_p)
     s = O.Solver(om, p)
     s.init_maxwellian(prim_for(case, t["input"]))
     dt = s.dt_cfl(case.cfl)
@@ -54,7 +55,8 @@ def gpu_solver(case, precision, engine=None):
     dm = D.Mesh(case.forest, case.solid)
     t = dm.tables()
     p = D.make_params(case.nv, case.vmax, precision=precision, scheme=case.scheme, collision=case.collision,
-                      tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow, t_wall=case.t_wall)
+                      tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow, t_wall=case.t_wall,
+                      korobov_p=case.korobov_p)
     s = D.Solver(dm, p)
     if engine is not None:
         s.engine(engine)

@@ -224,3 +224,26 @@ def test_tuner_cache_file_round_trip(tmp_path):
     assert "not a cache line" in lines and len(lines) == 4
     with pytest.raises(D.DvmError):
         D.tune_cache_put(path, "other", "gfx950", 12, 0, 0, (256, 0, 64, 0), 1.0)
+
+
+@pytest.mark.parametrize("nv,vmax,p", [(4, 3.0, 31), (8, 4.5, 127), (8, 4.5, 1021), (12, 6.0, 61)])
+def test_korobov_tables_bit_exact_vs_oracle(nv, vmax, p):
+    """the library's Korobov generator and trial tables (built on the host by
+    its own code) equal the oracle's, bit for bit"""
+    a = D.korobov_generator(p)
+    assert a == O.korobov_generator(p)
+    j, l, m = D.korobov_tables(nv, vmax, p, a)
+    jo, lo, mo, _ = O.korobov_tables((nv,) * 3, (-vmax,) * 3, (vmax,) * 3, p, a)
+    assert np.array_equal(j, jo) and np.array_equal(l, lo) and np.array_equal(m, mo)
+
+
+def test_korobov_solver_arguments_host_only():
+    f = I.uniform_forest((1, 1, 1), 1)
+    m = D.Mesh(f)
+    for kw, code in ((dict(nv=8, korobov_p=100), D.ERR_ARG),       # not prime
+                     (dict(nv=16, korobov_p=127), D.ERR_UNSUPPORTED),  # no kernel for 16^3
+                     (dict(nv=8, korobov_p=127, hybrid=True), D.ERR_UNSUPPORTED)):
+        nv = kw.pop("nv")
+        p = D.make_params(nv, 4.5, collision=D.COLL_KOROBOV, tau_or_kn=0.5, **kw)
+        h = __import__("ctypes").c_void_p()
+        assert D.lib().dvm_create_solver(m.h, __import__("ctypes").byref(p), __import__("ctypes").byref(h)) == code
