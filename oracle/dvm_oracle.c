@@ -23,6 +23,8 @@
  *                Or the Boltzmann collision integral of hard spheres on
  *                Korobov lattice nodes, eqs. (3)-(6) of section 3.2, with the
  *                same conservative correction (see or_korobov_tables()).
+ *                Or the lattice Boltzmann BGK collision of section 4 on the
+ *                D3Q19 / D3Q27 subsets of a 3x3x3 velocity grid.
  *
  * Everything is FP64.  f is stored cell-major in canonical velocity order
  * i = (kx*Ny + ky)*Nz + kz, cells in Morton order.  OpenMP parallelises the
@@ -600,6 +602,7 @@ typedef struct {
     double t_wall;    /* temperature of the diffuse wall (wall at rest) */
     int64_t korobov_p; /* collision 3: lattice points per velocity node (prime) */
     int64_t korobov_a; /* collision 3: lattice generator (0: the optimal one) */
+    int lbm_q;         /* collision 4: 19 (D3Q19) or 27 (D3Q27) */
 } or_params;
 
 /* Korobov tables of one velocity grid: per node i and trial k, the partner
@@ -810,6 +813,67 @@ static int korobov_integral(const or_vgrid *g, const or_korobov *t, const double
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Lattice Boltzmann subset (section 4)                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * The LBM module is a DVM solver on a minimal velocity set (section 4): here
+ * the 3x3x3 velocity grid on [-3/2, 3/2]^3, whose nodes are the lattice
+ * vectors c in {-1, 0, 1}^3 with unit node volume, so the DVM moments are the
+ * lattice sums rho = sum f, rho u = sum c f.  D3Q27 keeps all 27 nodes, D3Q19
+ * drops the 8 corners (their f is zero and stays zero).  Weights by |c|^2 =
+ * 0, 1, 2, 3: D3Q27 8/27, 2/27, 1/54, 1/216; D3Q19 1/3, 1/18, 1/36, 0.
+ * Equilibrium of section 4 (second-order expansion, cs^2 = 1/3):
+ *   f_eq = w rho (1 + c.u / cs^2 + (c.u)^2 / (2 cs^4) - |u|^2 / (2 cs^2)),
+ * BGK collision (collision 4): f' = f_eq + (f* - f_eq) exp(-dt / tau), rho and
+ * u from f*, tau = tau_or_kn.  Transport: the finite-volume upwind step of
+ * eq. (2) on the octree, unchanged.
+ */
+static double lbm_weight(int q, const double c[3]) {
+    int c2 = (int)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + 0.5);
+    if (q == 27) {
+        static const double w27[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+        return w27[c2];
+    }
+    static const double w19[4] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0, 0.0};
+    return w19[c2];
+}
+
+static int lbm_grid_ok(const or_params *p) {
+    if (p->lbm_q != 19 && p->lbm_q != 27) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (p->nv[a] != 3 || p->vlo[a] != -1.5 || p->vhi[a] != 1.5) return 0;
+    return 1;
+}
+
+static void lbm_equilibrium(const or_vgrid *g, int q, double rho, const double u[3], double *out) {
+    const double cs2 = 1.0 / 3.0;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int64_t v = 0; v < g->nv; ++v) {
+        double c[3];
+        vgrid_xi(g, v, c);
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        out[v] = lbm_weight(q, c) * rho * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    }
+}
+
+/* one LBM-BGK collision of a cell: rho, u of fs, exponential relaxation */
+static int lbm_collide(const or_vgrid *g, const or_params *p, double dt, const double *fs, double *out, double *work) {
+    double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+    for (int64_t v = 0; v < g->nv; ++v) {
+        double c[3];
+        vgrid_xi(g, v, c);
+        rho += fs[v];
+        for (int a = 0; a < 3; ++a) m[a] += c[a] * fs[v];
+    }
+    if (!(rho > 0.0)) { memcpy(out, fs, (size_t)g->nv * sizeof(double)); return OR_ERR_NONPHYSICAL; }
+    double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+    lbm_equilibrium(g, p->lbm_q, rho, u, work);
+    double e = exp(-dt / p->tau_or_kn);
+    for (int64_t v = 0; v < g->nv; ++v) out[v] = work[v] + (fs[v] - work[v]) * e;
+    return OR_OK;
+}
+
 static int64_t row_of(const or_solver *s, int64_t c) { return s->row ? s->row[c] : c; }
 static int64_t cell_of(const or_solver *s, int64_t r) { return s->cells ? s->cells[r] : r; }
 static const double *f_of(const or_solver *s, int64_t c) { return s->f + row_of(s, c) * s->g.nv; }
@@ -882,6 +946,7 @@ int or_solver_new_subset(const or_mesh *m, const or_params *p, int64_t n_sub, co
         rc = target_of_prim(pw, tgt);
         if (!rc) rc = corrected_maxwellian(&s->g, tgt, s->wall_m1);
     }
+    if (!rc && p->collision == 4 && !lbm_grid_ok(p)) rc = OR_ERR_ARG;
     if (!rc && p->collision == 3) {
         int64_t a = p->korobov_a ? p->korobov_a : or_korobov_generator(p->korobov_p);
         s->kt = korobov_build(&s->g, p->korobov_p, a);
@@ -905,6 +970,18 @@ int or_flag(const or_solver *s) { return s->flag; }
 void or_valid(const or_solver *s, uint8_t *out) {
     if (s->valid) memcpy(out, s->valid, (size_t)s->n_rows);
     else memset(out, 1, (size_t)s->n_rows);
+}
+
+/* LBM: f := f_eq(rho, u) per held cell; prim is [4][n_rows] (rho, ux, uy, uz) */
+int or_init_lbm(or_solver *s, const double *prim) {
+    if (s->p.collision != 4) return OR_ERR_ARG;
+    int64_t n = s->n_rows;
+    for (int64_t c = 0; c < n; ++c) {
+        double u[3] = {prim[1 * n + c], prim[2 * n + c], prim[3 * n + c]};
+        if (!(prim[c] > 0.0)) return OR_ERR_NONPHYSICAL;
+        lbm_equilibrium(&s->g, s->p.lbm_q, prim[c], u, s->f + c * s->g.nv);
+    }
+    return OR_OK;
 }
 
 /* f := corrected Maxwellian of (rho, ux, uy, uz, T) per held cell; prim is [5][n_rows] */
@@ -1113,6 +1190,7 @@ static int collide_cell(const or_vgrid *g, const or_params *p, const or_korobov 
                         double *out, double *work) {
     int64_t nv = g->nv;
     if (p->collision == 2) { memcpy(out, fs, (size_t)nv * sizeof(double)); return OR_OK; }
+    if (p->collision == 4) return lbm_collide(g, p, dt, fs, out, work);
     double mom[5], rho, u[3], T;
     moments_of(g, fs, mom);
     int rc = primitive_of(mom, &rho, u, &T);

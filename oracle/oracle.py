@@ -23,7 +23,7 @@ class OrParams(C.Structure):
     _fields_ = [("nv", C.c_int * 3), ("vlo", C.c_double * 3), ("vhi", C.c_double * 3),
                 ("scheme", C.c_int), ("collision", C.c_int), ("tau_mode", C.c_int),
                 ("tau_or_kn", C.c_double), ("inflow", C.c_double * 5), ("t_wall", C.c_double),
-                ("korobov_p", C.c_int64), ("korobov_a", C.c_int64)]
+                ("korobov_p", C.c_int64), ("korobov_a", C.c_int64), ("lbm_q", C.c_int)]
 
 
 def lib():
@@ -60,6 +60,7 @@ def lib():
         L.or_get_f.argtypes = [P, f64p]
         L.or_flag.argtypes = [P]
         L.or_init_maxwellian.argtypes = [P, f64p]
+        L.or_init_lbm.argtypes = [P, f64p]
         L.or_step.argtypes = [P, C.c_double, C.c_int]
         L.or_transport.argtypes = [P, C.c_double]
         L.or_moments.argtypes = [P, f64p]
@@ -164,7 +165,7 @@ class Mesh:
 
 
 def make_params(nv, vlo, vhi, scheme=0, collision=0, tau_mode=0, tau_or_kn=0.1,
-                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, korobov_p=0, korobov_a=0) -> OrParams:
+                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, korobov_p=0, korobov_a=0, lbm_q=0) -> OrParams:
     p = OrParams()
     for a in range(3):
         p.nv[a] = int(nv[a])
@@ -176,7 +177,14 @@ def make_params(nv, vlo, vhi, scheme=0, collision=0, tau_mode=0, tau_or_kn=0.1,
         p.inflow[a] = float(inflow[a])
     p.t_wall = float(t_wall)
     p.korobov_p, p.korobov_a = int(korobov_p), int(korobov_a)
+    p.lbm_q = int(lbm_q)
     return p
+
+
+def lbm_params(q, tau, collision=4, scheme=0):
+    """LBM on the octree: the D3Q19 / D3Q27 subset of the 3^3 grid on [-3/2, 3/2]^3"""
+    return make_params((3, 3, 3), (-1.5,) * 3, (1.5,) * 3, scheme=scheme, collision=collision, tau_or_kn=tau,
+                       lbm_q=q)
 
 
 class Solver:
@@ -214,6 +222,12 @@ class Solver:
         out = np.zeros(self.n * self.nv)
         lib().or_get_f(self.h, out)
         return out.reshape(self.n, self.nv)
+
+    def init_lbm(self, prim):
+        """LBM: f := f_eq of (rho, ux, uy, uz) [4][n]"""
+        rc = lib().or_init_lbm(self.h, np.ascontiguousarray(prim, np.float64).reshape(-1))
+        if rc:
+            raise RuntimeError(f"or_init_lbm: {rc}")
 
     def init_maxwellian(self, prim):
         rc = lib().or_init_maxwellian(self.h, np.ascontiguousarray(prim, np.float64).reshape(-1))
