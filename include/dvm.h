@@ -491,6 +491,55 @@ void dvm_destroy_mlp(dvm_mlp *net);
 int dvm_sensor(dvm_solver *s, const dvm_mlp *net, double kappa, uint8_t *mask, float *score, void *stream);
 int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double dt, double cfl, void *stream);
 
+/*
+ * Lattice Boltzmann subset (section 4: the LBM module as a DVM solver on a
+ * minimal velocity set).  D3Q19 or D3Q27 lattice vectors c in {-1, 0, 1}^3
+ * (D3Q19 without the 8 corners) on the same octree: each step is the
+ * finite-volume first-order upwind transport of eq. (2) for every lattice
+ * vector (periodic and outflow domain faces; a FINER face contributes the
+ * mean of its four leaves), then BGK relaxation toward the second-order
+ * equilibrium of section 4,
+ *   f_eq = w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 |u|^2)   (cs^2 = 1/3),
+ * weights by |c|^2 = 0, 1, 2, 3: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27,
+ * 1/54, 1/216; exponential (f_eq + (f* - f_eq) e^{-dt/tau}) or explicit
+ * Euler relaxation.  rho = sum f, rho u = sum c f (mass and momentum are
+ * conserved; the model is isothermal).
+ * Buffers (caller-owned, 256-byte aligned, sizes from dvm_lbm_buffer_sizes):
+ * two state buffers f[q][n_cells] (population-major, storage precision),
+ * moments [5][n_cells] FP64, tables (32-byte cell records and the FINER-face
+ * leaf lists), workspace (reduction partials, sums, flag).
+ * dvm_lbm_create -- DVM_ERR_UNSUPPORTED if the mesh has inflow or wall faces.
+ * dvm_lbm_init -- f := f_eq of prim[4][n_cells] (rho, ux, uy, uz; device FP64).
+ * dvm_lbm_step -- dt <= 0: dt = cfl h_min / max_i (|c_x| + |c_y| + |c_z|)
+ * (2 for D3Q19, 3 for D3Q27).
+ * dvm_lbm_moments -- out[5][n_cells] = (rho, rho u, sum |c|^2 f / 2).
+ * dvm_lbm_check -- synchronises; global sums sum_c V_c (moments) and the flag
+ * (rho <= 0 or NaN).
+ * dvm_lbm_get_f / dvm_lbm_set_f -- the current state as [n_cells][27] in the
+ * canonical order of the 3^3 grid (kx*9 + ky*3 + kz, c = k - 1), storage
+ * precision, corners zero for D3Q19.
+ */
+typedef struct dvm_lbm dvm_lbm;
+typedef struct {
+    int32_t q;                /* 19 or 27 */
+    int32_t precision;        /* DVM_PREC_* */
+    int32_t collision;        /* DVM_COLL_EXP or DVM_COLL_EULER */
+    double tau;               /* relaxation time */
+} dvm_lbm_params;
+int dvm_lbm_create(const dvm_mesh *m, const dvm_lbm_params *p, dvm_lbm **out);
+int dvm_lbm_buffer_sizes(const dvm_lbm *s, dvm_sizes *out);
+int dvm_lbm_bind(dvm_lbm *s, void *f_a, void *f_b, double *moments, void *tables, void *ws);
+int dvm_lbm_upload(dvm_lbm *s, void *stream);
+int dvm_lbm_init(dvm_lbm *s, const double *prim, void *stream);
+int dvm_lbm_dt(const dvm_lbm *s, double cfl, double *dt);
+int dvm_lbm_step(dvm_lbm *s, int32_t n_steps, double dt, double cfl, void *stream);
+int dvm_lbm_moments(dvm_lbm *s, double *out, void *stream);
+int dvm_lbm_check(dvm_lbm *s, void *stream, dvm_diag *out);
+int dvm_lbm_get_f(const dvm_lbm *s, void *out, void *stream);
+int dvm_lbm_set_f(dvm_lbm *s, const void *in, void *stream);
+int dvm_lbm_current_f(const dvm_lbm *s, void **f);
+void dvm_destroy_lbm(dvm_lbm *s);
+
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);
 int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, void *stream);

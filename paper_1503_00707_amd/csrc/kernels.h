@@ -142,6 +142,30 @@ void korobov_tables(int n, double vmax, int64_t p, int64_t a, std::vector<int32_
 void korobov_device_table(int nh, const std::vector<int32_t> &J, const std::vector<int32_t> &L,
                           const std::vector<int32_t> &M, int64_t p, std::vector<uint64_t> &out);
 
+// Lattice Boltzmann subset (lbm.hip / lbm.cpp).
+struct LbmCell {        // 32 bytes per cell
+    int32_t nb[6];      // the neighbour of a SAME or COARSER face (face order -x, +x, -y, +y, -z, +z)
+    uint32_t meta;      // face kinds, 3 bits per face (bits 0..17); level in bits 24..31
+    int32_t fine;       // first of the cell's FINER-face tuples (4 cells each, face order) in the fine list
+};
+static_assert(sizeof(LbmCell) == 32, "LbmCell must stay 32 bytes");
+struct LbmArgs {
+    const void *f_in;   // [Q][n]
+    void *f_out;
+    const LbmCell *cells;
+    const int32_t *fine;
+    int64_t n;
+    double dt, h0;
+    double relax;       // exp(-dt/tau) (exponential) or dt/tau (explicit Euler)
+    int euler;
+    int *flag;
+};
+hipError_t launch_lbm_step(int q, bool fp64, const LbmArgs &a, hipStream_t st);
+hipError_t launch_lbm_moments(int q, bool fp64, const void *f, const LbmCell *cells, int64_t n, double h0,
+                              double *mom, double *partials, double *sums, hipStream_t st);
+hipError_t launch_lbm_init(int q, bool fp64, const double *prim, void *f, int64_t n, int *flag, hipStream_t st);
+hipError_t launch_lbm_canon(int q, bool fp64, const void *src, void *dst, int64_t n, bool to_canon, hipStream_t st);
+
 // Deferred-collision engine (lazy_impl.h).
 struct UnitArgsPub {
     const void *f_in;

@@ -34,6 +34,9 @@ EXPORTED = [
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
     "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
     "dvm_mlp_gradient_noalloc", "dvm_korobov_generator", "dvm_korobov_tables",
+    "dvm_lbm_create", "dvm_lbm_buffer_sizes", "dvm_lbm_bind", "dvm_lbm_upload", "dvm_lbm_init", "dvm_lbm_dt",
+    "dvm_lbm_step", "dvm_lbm_moments", "dvm_lbm_check", "dvm_lbm_get_f", "dvm_lbm_set_f", "dvm_lbm_current_f",
+    "dvm_destroy_lbm",
 ]
 MLP_WEIGHTS, MLP_PARAMS = 4929, 4949
 
@@ -59,6 +62,10 @@ class Params(C.Structure):
                 ("collision", C.c_int32), ("tau_mode", C.c_int32), ("tau_or_kn", C.c_double),
                 ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32),
                 ("hybrid", C.c_int32), ("korobov_p", C.c_int32), ("korobov_a", C.c_int32)]
+
+
+class LbmParams(C.Structure):
+    _fields_ = [("q", C.c_int32), ("precision", C.c_int32), ("collision", C.c_int32), ("tau", C.c_double)]
 
 
 class Sizes(C.Structure):
@@ -115,6 +122,20 @@ def lib():
         L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
         L.dvm_save.argtypes = [P, P, C.c_char_p, P]
         L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_lbm_create.argtypes = [P, C.POINTER(LbmParams), C.POINTER(P)]
+        L.dvm_lbm_buffer_sizes.argtypes = [P, C.POINTER(Sizes)]
+        L.dvm_lbm_bind.argtypes = [P, P, P, P, P, P]
+        L.dvm_lbm_upload.argtypes = [P, P]
+        L.dvm_lbm_init.argtypes = [P, P, P]
+        L.dvm_lbm_dt.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
+        L.dvm_lbm_step.argtypes = [P, C.c_int32, C.c_double, C.c_double, P]
+        L.dvm_lbm_moments.argtypes = [P, P, P]
+        L.dvm_lbm_check.argtypes = [P, P, C.POINTER(Diag)]
+        L.dvm_lbm_get_f.argtypes = [P, P, P]
+        L.dvm_lbm_set_f.argtypes = [P, P, P]
+        L.dvm_lbm_current_f.argtypes = [P, C.POINTER(P)]
+        L.dvm_destroy_lbm.argtypes = [P]
+        L.dvm_destroy_lbm.restype = None
         L.dvm_korobov_generator.argtypes = [C.c_int64, C.POINTER(C.c_int64)]
         L.dvm_korobov_tables.argtypes = [C.c_int32, C.c_double, C.c_int64, C.c_int64, P, P, P]
         L.dvm_mlp_gradient_noalloc.argtypes = [P, P, P, C.c_int64, C.c_float, P, P, P]
@@ -418,6 +439,82 @@ class Solver:
                 lib().dvm_destroy_solver(self.h)
                 self.h = None
         except Exception:  # interpreter shutdown
+            pass
+
+
+class LBM:
+    """The lattice Boltzmann subset (dvm_lbm_*): D3Q19 or D3Q27 on a mesh, torch buffers."""
+
+    def __init__(self, mesh: Mesh, q=19, precision=PREC_FP32, tau=0.6, collision=COLL_EXP):
+        import torch
+        self.torch = torch
+        self.mesh = mesh
+        p = LbmParams(int(q), int(precision), int(collision), float(tau))
+        h = C.c_void_p()
+        _check(lib().dvm_lbm_create(mesh.h, C.byref(p), C.byref(h)), "dvm_lbm_create")
+        self.h = h
+        sz = Sizes()
+        _check(lib().dvm_lbm_buffer_sizes(h, C.byref(sz)), "dvm_lbm_buffer_sizes")
+        self.sizes = sz
+        self.n, self.q = int(sz.n_cells), int(q)
+        self.fdtype = torch.float64 if precision == PREC_FP64 else torch.float32
+
+        def buf(nbytes):
+            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+        self.f_a, self.f_b = buf(sz.f_bytes), buf(sz.f_bytes)
+        self.mom = torch.empty((5, self.n), dtype=torch.float64, device="cuda")
+        self.tables_buf = buf(sz.tables_bytes)
+        self.ws = buf(sz.ws_bytes)
+        _check(lib().dvm_lbm_bind(h, self.f_a.data_ptr(), self.f_b.data_ptr(), self.mom.data_ptr(),
+                                  self.tables_buf.data_ptr(), self.ws.data_ptr()), "dvm_lbm_bind")
+        _check(lib().dvm_lbm_upload(h, self.stream()), "dvm_lbm_upload")
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def init(self, prim):
+        """f := f_eq of prim [4][n] (rho, ux, uy, uz)"""
+        t = self.torch.as_tensor(np.ascontiguousarray(prim, np.float64)).to("cuda")
+        self._prim = t
+        _check(lib().dvm_lbm_init(self.h, t.data_ptr(), self.stream()), "dvm_lbm_init")
+
+    def dt(self, cfl):
+        out = C.c_double()
+        _check(lib().dvm_lbm_dt(self.h, float(cfl), C.byref(out)), "dvm_lbm_dt")
+        return out.value
+
+    def step(self, n=1, dt=0.0, cfl=0.5):
+        _check(lib().dvm_lbm_step(self.h, int(n), float(dt), float(cfl), self.stream()), "dvm_lbm_step")
+
+    def moments(self):
+        out = self.torch.empty((5, self.n), dtype=self.torch.float64, device="cuda")
+        _check(lib().dvm_lbm_moments(self.h, out.data_ptr(), self.stream()), "dvm_lbm_moments")
+        return out
+
+    def check(self):
+        d = Diag()
+        rc = lib().dvm_lbm_check(self.h, self.stream(), C.byref(d))
+        if rc not in (OK, ERR_NONPHYSICAL):
+            _check(rc, "dvm_lbm_check")
+        return rc, np.array(d.sums[:]), bool(d.nonphysical), int(d.steps)
+
+    def f_canonical(self):
+        out = self.torch.empty((self.n, 27), dtype=self.fdtype, device="cuda")
+        _check(lib().dvm_lbm_get_f(self.h, out.data_ptr(), self.stream()), "dvm_lbm_get_f")
+        return out
+
+    def set_f_canonical(self, f):
+        t = self.torch.as_tensor(np.ascontiguousarray(f)).to(device="cuda", dtype=self.fdtype)
+        _check(lib().dvm_lbm_set_f(self.h, t.data_ptr(), self.stream()), "dvm_lbm_set_f")
+        self.torch.cuda.synchronize()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().dvm_destroy_lbm(self.h)
+                self.h = None
+        except Exception:
             pass
 
 

@@ -5,8 +5,9 @@ velocities on [-4.5, 4.5]^3, each run's rho, u, T perturbed by random
 sinusoids (inputs.fields("sensor_runs")) and its relaxation time drawn
 log-uniform in [0.01, 1]; at every step the features of the moments
 (dvm_features) and the non-equilibrium measure r = |f - Mt| / |Mt|
-(dvm_labels) of a seeded subset of cells are kept; a cell is "kinetic"
-when r > 0.05.  Training: dvm_mlp_train_step (class-weighted BCE, Adam)
+(dvm_labels) of a seeded subset of cells are kept, the features before a
+step and r after it; a cell is "kinetic" when r > theta, theta calibrated
+against the hybrid's error bar.  Training: dvm_mlp_train_step (class-weighted BCE, Adam)
 over shuffled mini-batches.  Evaluation: the hybrid step driven by the
 sensor against full DVM on the same flow (moment error in the norm of
 max rho, max rho sqrt(max T), max E) and its time.
@@ -53,9 +54,12 @@ def generate(runs, seed0=0, steps=20, keep=256, precision=D.PREC_FP32, log=None)
         dt = s.dt(0.5)
         rng = np.random.default_rng([seed, 11])
         for _ in range(steps):
-            s.step(1, dt=dt)
+            # features of the state before the step, the label of the state after it:
+            # a cell can be fluid for this step if the kinetic run's next state is
+            # near its Maxwellian (otherwise turning it kinetic again loses that part)
             idx = torch.as_tensor(rng.choice(s.n, size=min(keep, s.n), replace=False), device="cuda")
             xs.append(s.features()[idx])
+            s.step(1, dt=dt)
             rs.append(s.labels()[idx])
         if log and (k + 1) % max(1, runs // 10) == 0:
             log(f"[sensor] generated {k + 1}/{runs} runs")
@@ -245,9 +249,11 @@ def lockstep(seed, policies, steps=20, level=4, nv=NV, vmax=VMAX, precision=D.PR
     kin = [0.0] * len(policies)
     ones = torch.ones(full.n, dtype=torch.uint8, device="cuda")
     for _ in range(steps):
+        full.step(1, dt=dt)
         r = None
         for k, (pol, h) in enumerate(zip(policies, hyb)):
             if pol[0] == "labels":
+                # the label the sensor is trained on: the kinetic run's state after this step
                 r = full.labels() if r is None else r
                 mask = (r > pol[1]).to(torch.uint8)
             elif pol[0] == "kn":
@@ -260,7 +266,6 @@ def lockstep(seed, policies, steps=20, level=4, nv=NV, vmax=VMAX, precision=D.PR
                 mask = ones
             kin[k] += float(mask.float().mean().item()) / steps
             h.hybrid_step(mask, n=1, dt=dt)
-        full.step(1, dt=dt)
     ref = full.moments().cpu().numpy()
     return [(_moment_error(h.moments().cpu().numpy(), ref), kin[k]) for k, h in enumerate(hyb)]
 
