@@ -79,20 +79,45 @@ def build_case(name):
     return w, forest, solid
 
 
-def gpu_bench(args):
+def sample_cells(tables, forest, rng, name, n_random=2):
+    """cells whose state is checked against the oracle: both sides of level
+    jumps, the density jump, the periodic wrap and random ones"""
+    n = tables["type"].shape[0]
+    ty = tables["type"]
+    x = _centres(forest)[tables["input"]]
+    h = forest.h0 / 2.0 ** forest.level[tables["input"]].astype(np.float64)
+    pools = [np.nonzero((ty == 2).any(1))[0], np.nonzero((ty == 1).any(1))[0]]
+    if name.startswith("octree"):
+        pools += [np.nonzero(np.abs(x[:, 0] - 0.5) < h)[0], np.nonzero(x[:, 0] < h)[0]]
+    picks = [rng.choice(p, 1) for p in pools if p.size]
+    picks.append(rng.choice(n, n_random, replace=False))
+    return np.unique(np.concatenate(picks)).astype(np.int64)
+
+
+def _centres(forest):
+    h = forest.h0 / (2.0 ** forest.level.astype(np.float64))
+    return (forest.ijk.astype(np.float64) + 0.5) * h[:, None]
+
+
+def gpu_bench(args, precision=None, steps=None, warmup=None, keep_samples=True, workload=None):
     import torch
 
     from paper_1503_00707_amd import dvm as D
     from paper_1503_00707_amd import inputs as I
 
+    precision = args.precision if precision is None else precision
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    workload = args.workload if workload is None else workload
     t0 = time.time()
-    w, forest, solid = build_case(args.workload)
+    w, forest, solid = build_case(workload)
     mesh = D.Mesh(forest, solid)
     t = mesh.tables()
     prim = I.fields(w.fields, I.leaf_centres(forest)[t["input"]], **w.field_args)
-    prec = D.PREC_FP64 if args.precision == "fp64" else D.PREC_FP32
+    prec = D.PREC_FP64 if precision == "fp64" else D.PREC_FP32
     p = D.make_params(w.nv[0], w.vhi[0], precision=prec, scheme=w.scheme, collision=w.collision,
-                      tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall)
+                      tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall,
+                      korobov_p=w.korobov_p)
     s = D.Solver(mesh, p)
     if args.shape:
         T, W, G, NT = (int(x) for x in args.shape.split(","))
@@ -101,7 +126,7 @@ def gpu_bench(args):
     del prim
     dt = s.dt(w.cfl)
     torch.cuda.synchronize()
-    log(f"[bench] {args.workload}: {s.n} cells x {s.nv} velocities, {args.precision}, "
+    log(f"[bench] {workload}: {s.n} cells x {s.nv} velocities, {precision}, "
         f"{2 * s.sizes.f_bytes / 1e9:.1f} GB of f, setup {time.time() - t0:.1f}s")
     s.global_sums()
     rc, g0, _, _ = s.check()
@@ -114,15 +139,15 @@ def gpu_bench(args):
             ev[1].record()
         s.global_sums()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_step()
     torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(f"[bench] warmup {warmup} done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         one_step(evs[i])
     end.record()
     torch.cuda.synchronize()
@@ -130,9 +155,20 @@ def gpu_bench(args):
     total_ms = evs[0][0].elapsed_time(end)
     k_ms = [a.elapsed_time(b) for a, b in evs]
     rc, g1, bad, nsteps = s.check()
-    log(f"[bench] timed {args.steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), "
+    log(f"[bench] timed {steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms), "
         f"step kernel mean {np.mean(k_ms):.3f} ms, status {rc}")
-    cvu = s.n * s.nv * args.steps / (total_ms / 1e3)
+    cvu = s.n * s.nv * steps / (total_ms / 1e3)
+    samples = None
+    if keep_samples:
+        # state of sampled cells after warmup + steps, for the oracle comparison (outside the timed region)
+        # the headline's samples also make the CPU baseline's bounded sample (10-30 s of oracle work)
+        cells = sample_cells(t, forest, np.random.default_rng(2024), workload,
+                             n_random=8 if workload == "octree64_v24_p40" and precision == "fp32" else 2)
+        idx = torch.as_tensor(cells, device="cuda")
+        # f only when a canonical copy of the whole state fits beside the two buffers
+        free = torch.cuda.mem_get_info()[0]
+        fs = s.f_canonical()[idx].double().cpu().numpy() if free > s.sizes.f_bytes + (4 << 30) else None
+        samples = dict(cells=cells, mom=s.moments()[:, idx].cpu().numpy(), f=fs, steps=warmup + steps, dt=dt)
     fbytes = 8 if prec == D.PREC_FP64 else 4
     # algorithmic bytes of one fused step: read f once, write f once per CVU
     alg_bytes = 2 * fbytes * s.n * s.nv
@@ -144,13 +180,60 @@ def gpu_bench(args):
               "cells without FINER/WALL faces, the full kernel over the rest; events bracket both"
               if split else "k_step (fused transport+moments+Maxwellian+BGK, one launch; cells without FINER/WALL "
               "faces take the reduced code path)")
-    return dict(cvu=cvu, total_ms=total_ms, k_ms=k_ms, achieved=achieved, alg_bytes=alg_bytes, n=s.n, nv=s.nv,
-                rc=rc, drift=drift, g0=g0, w=w, fbytes=fbytes, dt=dt, kernel=kernel)
+    del s, mesh
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return dict(cvu=cvu, total_ms=total_ms, k_ms=k_ms, achieved=achieved, alg_bytes=alg_bytes, n=len(t["input"]),
+                nv=int(np.prod(w.nv)), rc=rc, drift=drift, g0=g0, w=w, fbytes=fbytes, dt=dt, kernel=kernel,
+                samples=samples, forest=forest, solid=solid, steps=steps)
 
 
-def gpu_bench_batch(args):
+def gpu_bench_lbm(q=19, steps=10, warmup=2):
+    """The lattice Boltzmann subset (D3Q19) on the 996,150-cell octree of the
+    headline (FP32, periodic, rho = 1 + 0.05 sin 2 pi x, a small shear flow):
+    cell updates per second, and the step kernel against the HBM roofline
+    (algorithmic 2 Q 4 bytes per cell update: read f once, write f once)."""
+    import torch
+
+    from paper_1503_00707_amd import dvm as D
+    w, forest, solid = build_case("octree64_v24_p40")
+    mesh = D.Mesh(forest)
+    t = mesh.tables()
+    x = _centres(forest)[t["input"]]
+    prim = np.stack([1 + 0.05 * np.sin(2 * np.pi * x[:, 0]), 0.05 * np.sin(2 * np.pi * x[:, 1]),
+                     0.03 * np.cos(2 * np.pi * x[:, 2]), 0 * x[:, 0]])
+    s = D.LBM(mesh, q=q, precision=D.PREC_FP32, tau=2e-3)
+    s.init(prim)
+    dt = s.dt(0.5)
+    s.step(warmup, dt=dt)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record()
+        s.step(1, dt=dt)
+        e1.record()
+    torch.cuda.synchronize()
+    k_ms = [a.elapsed_time(b) for a, b in evs]
+    total_ms = evs[0][0].elapsed_time(evs[-1][1])
+    rc = s.check()[0]
+    cells = sample_cells(t, forest, np.random.default_rng(7), "octree")
+    idx = torch.as_tensor(cells, device="cuda")
+    smp = dict(cells=cells, mom=s.moments()[:, idx].cpu().numpy(), f=s.f_canonical()[idx].double().cpu().numpy(),
+               steps=warmup + steps, dt=dt, prim=prim)
+    alg = 2 * q * 4 * s.n
+    out = dict(n=s.n, q=q, ms=total_ms / steps, k_ms=float(np.mean(k_ms)), alg_bytes=alg,
+               achieved=alg / (float(np.mean(k_ms)) / 1e3) / 1e9, rc=rc, samples=smp, forest=forest, tau=2e-3)
+    del s, mesh
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def gpu_bench_batch(args, steps=None, warmup=None, reps=2):
     """64 independent periodic instances of uneven size and velocity grid,
     advanced by one recorded graph launch per step (after autotuning)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     import dataclasses
 
     import torch
@@ -160,11 +243,12 @@ def gpu_bench_batch(args):
 
     t0 = time.time()
     ws = I.batch_workloads(seed=4)
-    solvers, meshes = [], []
+    solvers, meshes, forests = [], [], []
     cvu_step, alg_bytes = 0, 0
     for w in ws:
         lev, ijk = D.balance(w.forest)
         f = dataclasses.replace(w.forest, level=lev, ijk=ijk)
+        forests.append(f)
         m = D.Mesh(f)
         t = m.tables()
         p = D.make_params(w.nv[0], w.vhi[0], precision=D.PREC_FP32, tau_mode=w.tau_mode, tau_or_kn=w.tau_or_kn)
@@ -179,23 +263,33 @@ def gpu_bench_batch(args):
     log(f"[bench] batch of {len(solvers)}: {sum(s.n for s in solvers)} cells, {cvu_step:.4g} CVU/step, "
         f"{alg_bytes / 2 / 1e9:.1f} GB per state buffer, setup {time.time() - t0:.1f}s")
     t1 = time.time()
-    b.tune(reps=2)
+    b.tune(reps=reps)
     log(f"[bench] tuned in {time.time() - t1:.1f}s: {b.groups()}")
     g0 = [s.check()[1] for s in solvers]
-    b.step(args.warmup)
+    b.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    b.step(args.steps)
+    b.step(steps)
     e1.record()
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
+    # the cheapest instance, whole, for the oracle comparison (outside the timed region)
+    k = int(np.argmin([s.n * s.nv for s in solvers]))
+    sample = dict(w=ws[k], forest=forests[k], mom=solvers[k].moments().cpu().numpy(),
+                  f=solvers[k].f_canonical().double().cpu().numpy(), steps=warmup + steps, dt=solvers[k].dt(0.5),
+                  cells=solvers[k].n, nv=solvers[k].nv)
     rcs = [s.check() for s in solvers]
     # mass and energy drift per instance relative to the instance's totals (momentum sums are ~0)
     drift = max(float(max(abs(r[1][0] - g[0]) / abs(g[0]), abs(r[1][4] - g[4]) / abs(g[4]))) for r, g in zip(rcs, g0))
     rc = min(r[0] for r in rcs)
-    return dict(cvu=cvu_step * args.steps / (total_ms / 1e3), total_ms=total_ms, alg_bytes=alg_bytes, rc=rc,
-                drift=drift, groups=b.groups(), n=sum(s.n for s in solvers), instances=len(solvers))
+    out = dict(cvu=cvu_step * steps / (total_ms / 1e3), total_ms=total_ms, alg_bytes=alg_bytes, rc=rc,
+               drift=drift, groups=b.groups(), n=sum(s.n for s in solvers), instances=len(solvers), sample=sample,
+               steps=steps)
+    del b, solvers, meshes
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_ceiling(gb=8.0, reps=5):
@@ -245,35 +339,151 @@ def copy_calibration(gb):
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(args):
-    """FP64 oracle on the host cores: the same construction on 16^3 roots."""
+def _moment_scale(mom):
+    """reading of "relative": (max rho, max rho sqrt(max T) for rho u, max E)"""
+    rho = mom[0]
+    u = mom[1:4] / rho
+    T = (2 * mom[4] / rho - (u * u).sum(0)) / 3
+    su = rho.max() * np.sqrt(T.max())
+    return np.array([rho.max(), su, su, su, mom[4].max()])
+
+
+def _cone_oracle(r, threads, log_every=True):
+    """The FP64 oracle on the face-hop cone of the sampled cells of a GPU run
+    (eq. 2 couples a cell to its face neighbours only, so after k steps a cell
+    depends on the cells within k hops): run for the same steps from the same
+    initial state.  Returns (moment error, f error, CVU, seconds, rows)."""
     from oracle import oracle as O
     from paper_1503_00707_amd import inputs as I
-    name = "octree16_v24_p40"
-    w = I.workload(name)
-    lev, ijk = O.balance(w.forest)
-    import dataclasses
-    forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
-    cores = len(os.sched_getaffinity(0))
-    cores = min(cores, 16)
-    O.set_threads(cores)
-    m = O.Mesh(forest)
-    t = m.tables()
-    p = O.make_params(w.nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
-                      tau_or_kn=w.tau_or_kn)
-    s = O.Solver(m, p)
-    s.init_maxwellian(I.fields(w.fields, I.leaf_centres(forest)[t["input"]], **w.field_args))
-    dt = s.dt_cfl(w.cfl)
-    n_steps, t_used = 0, 0.0
-    while t_used < args.cpu_seconds and n_steps < 50:
+    w, forest, solid, smp = r["w"], r["forest"], r["solid"], r["samples"]
+    om = O.Mesh(forest, solid)
+    ot = om.tables()
+    cells = om.cone(smp["cells"], smp["steps"])
+    op = O.make_params(w.nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
+                       tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall, korobov_p=w.korobov_p)
+    osub = O.Solver(om, op, cells)
+    prim = I.fields(w.fields, I.leaf_centres(forest)[ot["input"]][cells], **w.field_args)
+    osub.init_maxwellian(prim)
+    del prim
+    nv = osub.nv
+    t_used = 0.0
+    for k in range(smp["steps"]):
         t0 = time.perf_counter()
-        s.step(dt, 1)
+        rc = osub.step(smp["dt"], 1)
         t_used += time.perf_counter() - t0
-        n_steps += 1
-        log(f"[bench] oracle step {n_steps}: {t_used:.1f}s")
-    cvu = m.n_cells * s.nv * n_steps / t_used
-    return dict(value=cvu, unit="CVU/s", cores=int(O.get_threads()), kind="oracle",
-                sample=f"{name}: {m.n_cells} cells x {s.nv} velocities, FP64, {n_steps} steps, {t_used:.1f}s")
+        if log_every:
+            log(f"[bench] oracle step {k + 1}/{smp['steps']} on {cells.size} cells: {t_used:.1f}s")
+        if rc:
+            raise RuntimeError(f"oracle step failed: {rc}")
+    ok = osub.valid()
+    at = np.searchsorted(cells, smp["cells"])
+    assert ok[at].all(), "a sample left its cone"
+    mo = osub.moments()
+    scale = _moment_scale(mo[:, ok])
+    em = float((np.abs(smp["mom"] - mo[:, at]).max(axis=1) / scale).max())
+    ef = None
+    if smp["f"] is not None:
+        fo = osub.get_f()[at]
+        ef = float((np.abs(smp["f"] - fo).max(axis=1) / np.abs(fo).max(axis=1)).max())
+    return em, ef, cells.size * nv * smp["steps"], t_used, cells.size
+
+
+def _batch_oracle(b):
+    """the whole cheapest batch instance through the FP64 oracle"""
+    from oracle import oracle as O
+    from paper_1503_00707_amd import inputs as I
+    smp = b["sample"]
+    w, forest = smp["w"], smp["forest"]
+    om = O.Mesh(forest)
+    ot = om.tables()
+    op = O.make_params(w.nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
+                       tau_or_kn=w.tau_or_kn)
+    os_ = O.Solver(om, op)
+    os_.init_maxwellian(I.fields(w.fields, I.leaf_centres(forest)[ot["input"]], **w.field_args))
+    if os_.step(smp["dt"], smp["steps"]):
+        raise RuntimeError("oracle step failed")
+    mo = os_.moments()
+    em = float((np.abs(smp["mom"] - mo).max(axis=1) / _moment_scale(mo)).max())
+    ef = float(np.abs(smp["f"] - os_.get_f()).max() / np.abs(os_.get_f()).max())
+    return em, ef
+
+
+def _cone_oracle_lbm(r):
+    """the oracle's LBM on the face-hop cone of the sampled cells"""
+    from oracle import oracle as O
+    smp, forest = r["samples"], r["forest"]
+    om = O.Mesh(forest)
+    cells = om.cone(smp["cells"], smp["steps"])
+    osub = O.Solver(om, O.lbm_params(r["q"], r["tau"]), cells)
+    osub.init_lbm(smp["prim"][:, cells])
+    if osub.step(smp["dt"], smp["steps"]):
+        raise RuntimeError("oracle LBM step failed")
+    ok = osub.valid()
+    at = np.searchsorted(cells, smp["cells"])
+    assert ok[at].all(), "a sample left its cone"
+    mo = osub.moments()[:4]
+    em = float(np.abs(smp["mom"][:4] - mo[:, at]).max() / np.abs(mo[0, ok]).max())
+    fo = osub.get_f()[at]
+    ef = float(np.abs(smp["f"] - fo).max() / np.abs(fo).max())
+    return em, ef
+
+
+def cpu_leg(head, fp64=None, batch=None, korobov=None, lbm=None):
+    """The FP64 CPU oracle, timed on the host cores on a bounded sample of the
+    headline workload (the face-hop cone of the sampled cells over all the
+    steps the GPU took), which also gives the headline's error against the
+    oracle; then the errors of the FP64 and batch legs.  Threads: the CPU share
+    of one GPU on the box (16), or fewer if the affinity mask is smaller."""
+    from oracle import oracle as O
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    O.set_threads(cores)
+    em, ef, cvu, secs, rows = _cone_oracle(head, cores)
+    w = head["w"]
+    cpu = dict(value=cvu / secs, unit="CVU/s", cores=int(O.get_threads()), kind="oracle",
+               sample=f"{head['samples']['cells'].size} sampled cells of {w.name} and their "
+                      f"{head['samples']['steps']}-hop face cone: {rows} cells x {int(np.prod(w.nv))} velocities, "
+                      f"FP64, {head['samples']['steps']} steps, {secs:.1f}s")
+    errors = {"fp32_headline": dict(moments=em, f=ef, cells=int(head["samples"]["cells"].size),
+                                    steps=int(head["samples"]["steps"]))}
+    if fp64 is not None:
+        em64, ef64, _, _, _ = _cone_oracle(fp64, cores, log_every=False)
+        errors["fp64"] = dict(moments=em64, f=ef64, cells=int(fp64["samples"]["cells"].size),
+                              steps=int(fp64["samples"]["steps"]))
+    if korobov is not None:
+        emk, efk, _, _, _ = _cone_oracle(korobov, cores, log_every=False)
+        errors["korobov"] = dict(moments=emk, f=efk, cells=int(korobov["samples"]["cells"].size),
+                                 steps=int(korobov["samples"]["steps"]))
+    if lbm is not None:
+        eml, efl = _cone_oracle_lbm(lbm)
+        errors["lbm_d3q19"] = dict(moments=eml, f=efl, cells=int(lbm["samples"]["cells"].size),
+                                   steps=int(lbm["samples"]["steps"]))
+    if batch is not None:
+        emb, efb = _batch_oracle(batch)
+        errors["batch_instance"] = dict(moments=emb, f=efb, cells=int(batch["sample"]["cells"]),
+                                        velocities=int(batch["sample"]["nv"]), steps=int(batch["sample"]["steps"]))
+    return cpu, errors
+
+
+def gpu_hybrid():
+    """The sensor-driven kinetic/fluid hybrid against plain DVM on the C1 flow
+    (rho = 1 + 0.1 sin 2 pi x, tau = 0.1): on the C1 mesh (16^3 cells x 8^3
+    velocities) and on 32^3 cells x 24^3 velocities; full DVM on the same flow
+    is the judge of the error.  Needs the committed trained sensor."""
+    from paper_1503_00707_amd import sensor_train as T
+    if not os.path.exists(T.TRAINED):
+        return None
+    net, meta = T.load_trained()
+    out = {"sensor": dict(label_threshold=meta["label_threshold"], logit_shift=meta["logit_shift"],
+                          trained_runs=meta["runs"])}
+    for name, level, nv, vmax in (("c1_16^3_v8", 4, 8, 4.5), ("c1flow_32^3_v24", 5, 24, 6.0)):
+        r = T.evaluate(net, level=level, nv=nv, vmax=vmax, graph=True)
+        n_cells, n_v = (2 ** level) ** 3, nv ** 3
+        r["cells"], r["velocities"] = n_cells, n_v
+        r["cvu_per_s_hybrid"] = n_cells * n_v / (r["ms_hybrid"] / 1e3)
+        r["cvu_per_s_plain"] = n_cells * n_v / (r["ms_full"] / 1e3)
+        out[name] = r
+        log(f"[bench] hybrid {name}: {r}")
+    return out
 
 
 def main():
@@ -283,8 +493,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="octree64_v24_p40")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the errors against the oracle)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="time only the headline (no FP64, batch and hybrid legs)")
     ap.add_argument("--shape", default="", help="threads,wpe,xcd_group,nt_store of the step kernel")
     ap.add_argument("--copy-calibration-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (read + write), for counter calibration")
@@ -295,6 +507,19 @@ def main():
         sys.exit(2)
     if args.copy_calibration_gb > 0:
         copy_calibration(args.copy_calibration_gb)
+    if args.workload == "lbm_d3q19":
+        rl = gpu_bench_lbm(steps=args.steps, warmup=args.warmup)
+        out = {"metric": METRIC, "value": rl["n"] / (rl["ms"] / 1e3), "unit": "cell updates/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": rl["ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "lbm_d3q19", "cells": rl["n"], "q": 19},
+               "roofline": {"bound": "hbm", "kernel": "k_lbm<float, 19>", "achieved": rl["achieved"],
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rl["achieved"] / HBM_PEAK_GBS,
+                            "traffic": None, "algorithmic_bytes_per_launch": rl["alg_bytes"],
+                            "kernel_ms_mean": rl["k_ms"]},
+               "status": int(rl["rc"])}
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "batch64":
         r = gpu_bench_batch(args)
         ms = r["total_ms"] / args.steps
@@ -316,12 +541,56 @@ def main():
     r = gpu_bench(args)
     copy_gbs = copy_ceiling()
     log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    secondary, r64, rb, rk, rl = {}, None, None, None, None
+    headline_default = args.workload == "octree64_v24_p40" and args.precision == "fp32" and not args.shape
+    if not args.no_secondary and headline_default:
+        # the other precisions and modes of the metric, each after the headline's buffers are freed
+        r64 = gpu_bench(args, precision="fp64", steps=3, warmup=1)
+        ms64 = r64["total_ms"] / r64["steps"]
+        secondary["fp64"] = {
+            "workload": args.workload, "precision": "FP64 f, moments, Maxwellian", "steps": r64["steps"],
+            "warmup": 1, "ms_per_step": ms64, "value": r64["cvu"], "unit": "CVU/s",
+            "roofline": {"bound": "hbm", "kernel": "k_step<double> (fused)", "achieved": r64["achieved"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r64["achieved"] / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": r64["alg_bytes"],
+                         "kernel_ms_mean": float(np.mean(r64["k_ms"]))},
+            "status": int(r64["rc"])}
+        rb = gpu_bench_batch(args, steps=3, warmup=1, reps=1)
+        msb = rb["total_ms"] / rb["steps"]
+        secondary["batch64"] = {
+            "workload": "batch64", "instances": rb["instances"], "cells": rb["n"], "steps": rb["steps"],
+            "warmup": 1, "ms_per_step": msb, "value": rb["cvu"], "unit": "CVU/s",
+            "graph": "one hipGraph launch per step (all velocity-grid groups + global sums)",
+            "roofline": {"bound": "hbm", "kernel": "batched step graph", "achieved": rb["alg_bytes"] / (msb / 1e3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": rb["alg_bytes"] / (msb / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": rb["alg_bytes"]},
+            "groups": rb["groups"], "status": int(rb["rc"])}
+        hy = gpu_hybrid()
+        secondary["hybrid"] = hy if hy is not None else "no trained sensor (paper_1503_00707_amd/sensor_net.json)"
+        # the Boltzmann collision integral on Korobov nodes (section 3.2), C1 mesh and flow, FP64
+        rk = gpu_bench(args, precision="fp64", steps=4, warmup=1, workload="korobov16_v8")
+        trials = rk["n"] * rk["nv"] * 1021
+        secondary["korobov"] = {
+            "workload": "korobov16_v8", "cells": rk["n"], "velocities": rk["nv"], "lattice_points": 1021,
+            "precision": "FP64", "steps": rk["steps"], "ms_per_step": rk["total_ms"] / rk["steps"],
+            "value": rk["cvu"], "unit": "CVU/s",
+            "trial_evaluations_per_s": trials / (float(np.mean(rk["k_ms"])) / 1e3),
+            "note": "step = transport kernel + k_korobov (eqs. 4-6); kernel times in profiles/", "status": int(rk["rc"])}
+        rl = gpu_bench_lbm()
+        secondary["lbm_d3q19"] = {
+            "workload": "octree64 p40 mesh, D3Q19, FP32", "cells": rl["n"], "q": rl["q"], "steps": 10,
+            "ms_per_step": rl["ms"], "value": rl["n"] / (rl["ms"] / 1e3), "unit": "cell updates/s",
+            "roofline": {"bound": "hbm", "kernel": "k_lbm<float, 19>", "achieved": rl["achieved"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rl["achieved"] / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": rl["alg_bytes"], "kernel_ms_mean": rl["k_ms"]},
+            "status": int(rl["rc"])}
+    cpu, errors = (None, None) if args.no_cpu_baseline else cpu_leg(
+        r, r64, rb, rk if secondary else None, rl if secondary else None)
     w = r["w"]
     ms = r["total_ms"] / args.steps
     # the committed counter profile covers the default workload and launch shape only
-    traffic = (measured_traffic(r["alg_bytes"])
-               if args.workload == "octree64_v24_p40" and args.precision == "fp32" and not args.shape else None)
+    traffic = measured_traffic(r["alg_bytes"]) if headline_default else None
     out = {
         "metric": METRIC,
         "value": r["cvu"],
@@ -350,6 +619,10 @@ def main():
         "conservation_drift_rel": {"mass": float(r["drift"][0]), "energy": float(r["drift"][4])},
         "status": int(r["rc"]),
     }
+    if errors is not None:
+        out["error_vs_oracle"] = errors
+    if secondary:
+        out["secondary"] = secondary
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -394,6 +394,14 @@ int dvm_batch_workspace_bytes(const dvm_batch *b, size_t *bytes);
 int dvm_batch_bind(dvm_batch *b, void *ws);
 int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream);
 int dvm_batch_tune(dvm_batch *b, int32_t reps, const char *cache_path, void *stream);
+/*
+ * dvm_batch_branches -- record the velocity-grid groups of a batched step as
+ * parallel branches of the graph (enable = 1, the default: the groups run
+ * concurrently, the global sums after all of them) or as one chain
+ * (enable = 0).  The results are the same bitwise (the groups share no data).
+ * enable < 0 only queries; *previous (may be NULL) receives the setting.
+ */
+int dvm_batch_branches(dvm_batch *b, int32_t enable, int32_t *previous);
 int dvm_batch_info(const dvm_batch *b, int32_t group, int32_t *nh, int32_t *n_inst, int64_t *n_cells,
                    int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store, double *tuned_ms);
 void dvm_destroy_batch(dvm_batch *b);

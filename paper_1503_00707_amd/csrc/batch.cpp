@@ -38,6 +38,7 @@ struct dvm_batch {
     size_t ws_bytes = 0;
     char *ws = nullptr;
     bool args_valid = false;
+    bool branches = true;          // groups on parallel graph branches (else one chain)
     int phase = 0;                 // buffer parity of the next step
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     // host copy of the argument block (kept alive for the asynchronous upload)
@@ -102,11 +103,46 @@ hipError_t enqueue_step(const dvm_batch *b, int ph, hipStream_t st) {
                                     kPartials, st);
 }
 
+// The step with the velocity-grid groups on parallel branches: group k > 0 is
+// enqueued on side stream k - 1, forked from and joined back into st by
+// events, so that in the recorded graph the groups' kernels are independent
+// nodes (the instances of different groups share no data) and run
+// concurrently; the global sums follow the join.
+hipError_t enqueue_step_branches(const dvm_batch *b, int ph, hipStream_t st, const std::vector<hipStream_t> &side,
+                                 const std::vector<hipEvent_t> &ev) {
+    hipError_t e = hipEventRecord(ev[0], st);
+    for (size_t k = 1; k < b->groups.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(side[k - 1], ev[0], 0);
+    for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k)
+        e = enqueue_group(b, b->groups[k], ph, b->groups[k].cfg, k == 0 ? st : side[k - 1]);
+    for (size_t k = 1; k < b->groups.size() && e == hipSuccess; ++k) {
+        e = hipEventRecord(ev[k], side[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[k], 0);
+    }
+    if (e != hipSuccess) return e;
+    return launch_global_sums_batch(reinterpret_cast<const SumArgs *>(b->ws + b->off_sums[0]), int(b->s.size()),
+                                    kPartials, st);
+}
+
 int build_graphs(dvm_batch *b) {
     hipStream_t cap;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    // side streams and events of the parallel branches (default priority)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
     int rc = DVM_OK;
+    for (size_t k = 1; k < b->groups.size() && rc == DVM_OK; ++k) {
+        hipStream_t x;
+        e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) rc = hip_fail(e, "hipStreamCreate");
+        else side.push_back(x);
+    }
+    for (size_t k = 0; k < b->groups.size() && rc == DVM_OK; ++k) {
+        hipEvent_t x;
+        e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_fail(e, "hipEventCreate");
+        else ev.push_back(x);
+    }
     for (int ph = 0; ph < 2 && rc == DVM_OK; ++ph) {
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -114,7 +150,7 @@ int build_graphs(dvm_batch *b) {
             rc = hip_fail(e, "hipStreamBeginCapture");
             break;
         }
-        hipError_t el = enqueue_step(b, ph, cap);
+        hipError_t el = b->branches ? enqueue_step_branches(b, ph, cap, side, ev) : enqueue_step(b, ph, cap);
         e = hipStreamEndCapture(cap, &graph);
         if (el != hipSuccess) rc = hip_fail(el, "batched step (capture)");
         else if (e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
@@ -125,6 +161,8 @@ int build_graphs(dvm_batch *b) {
         if (graph) (void)hipGraphDestroy(graph);
     }
     (void)hipStreamDestroy(cap);
+    for (auto x : side) (void)hipStreamDestroy(x);
+    for (auto x : ev) (void)hipEventDestroy(x);
     if (rc != DVM_OK) b->drop_graphs();
     return rc;
 }
@@ -330,6 +368,18 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, const char *cache_path, void *str
     for (auto *s : b->s) {
         hipError_t e = launch_moments(s->fp64, s->f[s->cur], s->mom, s->n, s->g, st);
         if (e != hipSuccess) return hip_fail(e, "moments");
+    }
+    return DVM_OK;
+}
+
+int dvm_batch_branches(dvm_batch *b, int32_t enable, int32_t *previous) {
+    clear_error();
+    if (!b) return fail(DVM_ERR_ARG, "null batch");
+    if (previous) *previous = b->branches ? 1 : 0;
+    if (enable < 0) return DVM_OK;
+    if ((enable != 0) != b->branches) {
+        b->branches = enable != 0;
+        b->drop_graphs();  // re-record at the next step
     }
     return DVM_OK;
 }

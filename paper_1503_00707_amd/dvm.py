@@ -34,7 +34,7 @@ EXPORTED = [
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
     "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
     "dvm_mlp_gradient_noalloc", "dvm_korobov_generator", "dvm_korobov_tables",
-    "dvm_lbm_create", "dvm_lbm_buffer_sizes", "dvm_lbm_bind", "dvm_lbm_upload", "dvm_lbm_init", "dvm_lbm_dt",
+    "dvm_batch_branches", "dvm_lbm_create", "dvm_lbm_buffer_sizes", "dvm_lbm_bind", "dvm_lbm_upload", "dvm_lbm_init", "dvm_lbm_dt",
     "dvm_lbm_step", "dvm_lbm_moments", "dvm_lbm_check", "dvm_lbm_get_f", "dvm_lbm_set_f", "dvm_lbm_current_f",
     "dvm_destroy_lbm",
 ]
@@ -122,6 +122,7 @@ def lib():
         L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
         L.dvm_save.argtypes = [P, P, C.c_char_p, P]
         L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_batch_branches.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_lbm_create.argtypes = [P, C.POINTER(LbmParams), C.POINTER(P)]
         L.dvm_lbm_buffer_sizes.argtypes = [P, C.POINTER(Sizes)]
         L.dvm_lbm_bind.argtypes = [P, P, P, P, P, P]
@@ -545,6 +546,12 @@ class Batch:
         the tuner cache file take the stored shape"""
         cp = None if cache_path is None else os.fsencode(cache_path)
         _check(lib().dvm_batch_tune(self.h, int(reps), cp, self.stream()), "dvm_batch_tune")
+
+    def branches(self, enable=-1):
+        """groups as parallel graph branches (1) or one chain (0); -1 queries"""
+        prev = C.c_int32(0)
+        _check(lib().dvm_batch_branches(self.h, int(enable), C.byref(prev)), "dvm_batch_branches")
+        return prev.value
 
     def groups(self):
         n = C.c_int32(0)

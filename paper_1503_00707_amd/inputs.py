@@ -60,6 +60,7 @@ class Workload:
     fields: str = "uniform"    # name of the initial-field recipe
     field_args: dict = dataclasses.field(default_factory=dict)
     solid_ball: Optional[tuple] = None          # (cx, cy, cz, r, level) -> solid leaves
+    korobov_p: int = 0                          # collision COLL_KOROBOV: lattice points per node
 
 
 # ----------------------------------------------------------------------------
@@ -258,6 +259,11 @@ def workload(name: str) -> Workload:
         return Workload(name, uniform_forest((1, 1, 1), 4, 1.0), (8, 8, 8), (-4.5,) * 3, (4.5,) * 3,
                         SCHEME_UPWIND1, COLL_EXP, TAU_CONST, 0.1, 0.5, 20, fields="sine_rho",
                         field_args={"a": 0.1})
+    if name == "korobov16_v8":
+        # the C1 mesh and flow with the Boltzmann collision integral on 1021 Korobov nodes per velocity
+        return Workload(name, uniform_forest((1, 1, 1), 4, 1.0), (8, 8, 8), (-4.5,) * 3, (4.5,) * 3,
+                        SCHEME_UPWIND1, COLL_KOROBOV, TAU_CONST, 0.5, 0.5, 4, fields="sine_rho",
+                        field_args={"a": 0.1}, korobov_p=1021)
     if name == "sphere32_v24_muscl":
         # 32^3 roots, two levels at a ball r = 0.2, Mach-2 inflow at x = 0
         u_in = 2.0 * math.sqrt(5.0 / 3.0)

@@ -311,21 +311,21 @@ def load_trained(path=TRAINED):
     return D.MLP(p, max_batch=16), meta
 
 
-def build_trained(runs=2000, epochs=10, calib_seeds=range(0, 48), eval_seeds=range(10000, 10064), log=None,
+def build_trained(runs=2000, epochs=10, calib_seeds=range(0, 160), eval_seeds=range(10000, 10064), log=None,
                   path=TRAINED):
     """The committed sensor: calibrate the label threshold against the error
     bar (exact labels as masks), generate the training data, train, calibrate
     the decision threshold of the network and the Kn_GLL baseline's kappa on
     the same calibration runs, evaluate on held-out flows; write `path`."""
     t0 = time.time()
-    thetas = [0.001, 0.002, 0.004, 0.008, 0.016, 0.032, 0.05]
+    thetas = [0.0005, 0.001, 0.0015, 0.002, 0.003, 0.004, 0.008]
     theta, th_table = calibrate(lambda v: ("labels", v), thetas, calib_seeds, log=log, name="label theta")
     x, r = generate(runs, seed0=0, log=log)
     if log:
         log(f"[sensor] {x.shape[0]} samples, kinetic at theta {theta}: {float((r > theta).float().mean()):.3f} "
             f"({time.time() - t0:.0f}s)")
     net, hist, pw = train(x, r, epochs=epochs, log=log, threshold=theta)
-    shifts = [-6.0, -4.0, -3.0, -2.0, -1.0, 0.0, 1.0, 2.0]
+    shifts = [-3.0, -2.0, -1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0]
     shift, sh_table = calibrate(lambda v: ("net", net_with_logit_shift(net, v)), shifts, calib_seeds, log=log,
                                 name="logit shift")
     tuned = net_with_logit_shift(net, shift)

@@ -80,6 +80,26 @@ def test_batch_graph_replays_match_eager_with_work_between():
             assert np.array_equal(s1.mom.cpu().numpy(), s2.mom.cpu().numpy()), rep
 
 
+def test_batch_branches_and_chain_agree_bitwise():
+    """the velocity-grid groups recorded as parallel graph branches (default)
+    and as one chain advance every instance identically, replay after replay"""
+    import torch
+    inst = _instances(14, 6, D.PREC_FP32)
+    a_side = [_solver(w, f, D.PREC_FP32) for w, f in inst]
+    b_side = [_solver(w, f, D.PREC_FP32) for w, f in inst]
+    ba = D.Batch([s for _, s in a_side])
+    bb = D.Batch([s for _, s in b_side])
+    assert len(ba.groups()) >= 2
+    assert ba.branches() == 1 and bb.branches(0) == 1 and bb.branches() == 0
+    for rep in range(3):
+        ba.step(2)
+        bb.step(2)
+        torch.cuda.synchronize()
+        for (_, s1), (_, s2) in zip(a_side, b_side):
+            assert np.array_equal(_state(s1)[0], _state(s2)[0]), rep
+            assert np.array_equal(s1.check()[1], s2.check()[1]), rep
+
+
 def test_batch_picks_up_instances_stepped_alone():
     import torch
     inst = _instances(13, 3, D.PREC_FP64)

