@@ -700,14 +700,32 @@ struct HybHook {
     }
 };
 
+// Kinetic cells (fluid cells: k_fluid_update), in the XCD-aware cell order
+// of the plain step.  A kinetic cell with no fluid face neighbour has nothing
+// to record and runs exactly the plain step's code (the reduced code when it
+// has no FINER or WALL face); one next to a fluid cell runs the full code with
+// the interface-flux hook.  All three compute the same step, bitwise.
 template <typename F, int NH, int T, int WPE, int FENCE, bool NT>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step_hybrid(StepArgs a,
                                                                                                HybArgs h) {
     __shared__ StepSmem<F, NH, T> sm;
-    const int64_t c = blockIdx.x;
-    if (!h.mask[c]) return;  // fluid cells: k_fluid_update
-    const HybHook hook{h};
-    step_cell<F, NH, T, FENCE, NT, false, false, HybHook>(a, c, sm, hook);
+    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
+    if (!h.mask[c]) return;
+    const CellView cell(a.cells, c);
+    bool fluid_nb = false;
+    for (int f = 0; f < 6; ++f) {
+        const int ty = cell.type_rt(f);
+        const int k = ty == DVM_FACE_FINER ? 4 : (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) ? 1 : 0;
+        for (int q = 0; q < k; ++q) fluid_nb |= h.mask[cell.nbr_rt(f, q)] == 0;
+    }
+    if (fluid_nb) {
+        const HybHook hook{h};
+        step_cell<F, NH, T, FENCE, NT, false, false, HybHook>(a, c, sm, hook);
+    } else if (needs_correction(a.cells, c)) {
+        step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
+    } else {
+        step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
+    }
 }
 
 // Fluid cells, one thread each: U' = U - dt/h sum_faces (H_out + H_in).
@@ -786,7 +804,7 @@ hipError_t hybrid_dispatch(const StepArgs &a, const HybArgs &h, hipStream_t st) 
         hipLaunchKernelGGL((k_hybrid_rows<F, NH, T>), grid, dim3(T), 0, st, a, h);               \
         e = hipGetLastError();                                                                     \
         if (e != hipSuccess) return e;                                                             \
-        hipLaunchKernelGGL((k_step_hybrid<F, NH, T, W, FN, false>), grid, dim3(T), 0, st, a, h); \
+        hipLaunchKernelGGL((k_step_hybrid<F, NH, T, W, FN, true>), grid, dim3(T), 0, st, a, h); \
         break;
     switch (a.g.nh) {
         DVM_HYB(2, 64, 4, 0)
