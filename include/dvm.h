@@ -548,6 +548,50 @@ int dvm_lbm_set_f(dvm_lbm *s, const void *in, void *stream);
 int dvm_lbm_current_f(const dvm_lbm *s, void **f);
 void dvm_destroy_lbm(dvm_lbm *s);
 
+/*
+ * On-device mesh adaptation (section 3.1 step 4: the cell order and the
+ * stencil are rebuilt each time the mesh changes; section 3.3: on the device).
+ * Meshes without solid leaves.  The library allocates nothing: the caller
+ * passes a device workspace of dvm_adapt_workspace_bytes(max_leaves) bytes.
+ * dvm_adapt_leaves -- from the solver's mesh and per-cell flags (device,
+ * int8: +1 refine into 8 children, -1 coarsen: a complete set of 8 sibling
+ * leaves that all ask is replaced by their parent, 0 keep), then the 2:1
+ * closure over faces, edges and corners (section 2.1; more leaves are
+ * refined as needed): the new leaves in Morton order into level_out[cap],
+ * ijk_out[cap][3] (device); *n_out (host) their number.  DVM_ERR_WORKSPACE if
+ * more than cap (then *n_out is the number needed).  Synchronises.
+ * dvm_adapt_mesh -- the mesh record of an adapted leaf list (device arrays
+ * from dvm_adapt_leaves, n leaves): domain and boundary kinds of `old`, the
+ * leaf list copied to the host (13 bytes per leaf, for the solver's sizes and
+ * checkpoints) and NO host face tables: each solver on it gets its tables from
+ * dvm_adapt_tables.  dvm_mesh_export refuses to export its tables and the LBM
+ * path refuses it; destroy with dvm_destroy_mesh.  Synchronises.
+ * dvm_adapt_tables -- the face tables of a solver on the adapted leaf list,
+ * built on the device from the device leaf list (Morton order) into the
+ * solver's bound tables buffer (the same records the host builder makes), and
+ * the step's selection list of regular cells; the mesh's face counts
+ * (dvm_mesh_info) are set from them.  Call after dvm_upload: a solver on a
+ * dvm_adapt_mesh mesh is not ready (DVM_ERR_WORKSPACE "call dvm_upload first"
+ * from every other call) until this returns DVM_OK.  On a solver of a mesh
+ * made by dvm_create_mesh of the same list it rewrites the same bytes.
+ * DVM_ERR_UNBALANCED if the list is not a 2:1-balanced partition.
+ * Synchronises.
+ * dvm_adapt_remap -- the current state of `to` from the current state of
+ * `from` (same domain, velocity grid and precision): a new cell inside an old
+ * leaf takes its row, a new cell covering several old leaves their
+ * volume-weighted mean (FP64 sums in key order), so mass, momentum and energy
+ * are conserved; then `to`'s moments are recomputed.  Workspace: the two leaf
+ * lists and their keys (dvm_adapt_workspace_bytes(n_from + n_to) is enough).
+ */
+int dvm_adapt_workspace_bytes(int64_t max_leaves, size_t *bytes);
+int dvm_adapt_leaves(const dvm_solver *s, const int8_t *flags, int64_t cap, uint8_t *level_out, int32_t *ijk_out,
+                     int64_t *n_out, void *ws, size_t ws_bytes, void *stream);
+int dvm_adapt_mesh(const dvm_mesh *old, const uint8_t *level, const int32_t *ijk, int64_t n, dvm_mesh **out,
+                   void *stream);
+int dvm_adapt_tables(dvm_solver *s, const uint8_t *level, const int32_t *ijk, void *ws, size_t ws_bytes,
+                     void *stream);
+int dvm_adapt_remap(const dvm_solver *from, dvm_solver *to, void *ws, size_t ws_bytes, void *stream);
+
 /* canonical <-> internal velocity order of one state buffer [n_cells][N^3] */
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream);
 int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, void *stream);

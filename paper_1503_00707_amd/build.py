@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdvm.so")
 SOURCES = ["csrc/mesh.cpp", "csrc/solver.cpp", "csrc/batch.cpp", "csrc/sensor.cpp", "csrc/persist.cpp", "csrc/korobov.cpp", "csrc/lbm.cpp", "csrc/kernels_misc.hip",
-           "csrc/kernels_f32.hip", "csrc/kernels_f64.hip", "csrc/sensor.hip", "csrc/korobov.hip", "csrc/lbm.hip"]
+           "csrc/kernels_f32.hip", "csrc/kernels_f64.hip", "csrc/sensor.hip", "csrc/korobov.hip", "csrc/lbm.hip", "csrc/adapt.hip"]
 
 
 def build(verbose: bool = False, jobs: int = 3) -> str:

@@ -43,7 +43,8 @@ struct dvm_mesh {
     int32_t finest;
     int64_t n_leaves;
     std::vector<dvm::Leaf> cells;     // fluid leaves, Morton order
-    std::vector<dvm::DevCell> table;  // one record per cell
+    std::vector<dvm::DevCell> table;  // one record per cell (empty when device_tables)
     double h_min;
     int64_t n_faces[6];
+    bool device_tables = false;       // face tables built on the device by each solver (dvm_adapt_tables)
 };

@@ -53,6 +53,7 @@ int dvm_lbm_create(const dvm_mesh *m, const dvm_lbm_params *p, dvm_lbm **out) {
     if (p->collision != DVM_COLL_EXP && p->collision != DVM_COLL_EULER)
         return fail(DVM_ERR_ARG, "collision must be DVM_COLL_EXP or DVM_COLL_EULER");
     if (!(p->tau > 0)) return fail(DVM_ERR_ARG, "tau must be > 0");
+    if (m->device_tables) return fail(DVM_ERR_UNSUPPORTED, "the LBM path needs a mesh built by dvm_create_mesh");
     if (m->n_faces[DVM_FACE_INFLOW] || m->n_faces[DVM_FACE_WALL])
         return fail(DVM_ERR_UNSUPPORTED, "the LBM path has periodic and outflow boundaries only");
     dvm_lbm *s = new (std::nothrow) dvm_lbm();

@@ -330,6 +330,8 @@ int dvm_mesh_info(const dvm_mesh *m, dvm_mesh_info_t *out) {
 int dvm_mesh_export(const dvm_mesh *m, int64_t *input, uint64_t *key, uint8_t *type, int32_t *nbr) {
     clear_error();
     if (!m) return fail(DVM_ERR_ARG, "null mesh");
+    if (m->device_tables && (type || nbr))
+        return fail(DVM_ERR_UNSUPPORTED, "this mesh's face tables live on the device (dvm_adapt_tables)");
     for (size_t c = 0; c < m->cells.size(); ++c) {
         if (input) input[c] = m->cells[c].input;
         if (key) key[c] = m->cells[c].key;

@@ -104,6 +104,16 @@ hipError_t dvm::solver_make_plain(dvm_solver *s, hipStream_t st) {
     return hipSuccess;
 }
 
+hipError_t dvm::solver_state_replaced(dvm_solver *s, hipStream_t st) {
+    s->lazy_valid = false;
+    s->relax_pending = false;
+    hipError_t e = ensure_lazy(s, st);
+    if (e == hipSuccess) e = solver_reset_hybrid(s, st);
+    if (e == hipSuccess) e = launch_moments(s->fp64, s->f[s->cur], s->mom, s->n, s->g, st);
+    s->hybrid_fluid = false;
+    return e;
+}
+
 double dvm::solver_max_speed_sum(const dvm_solver *s) {
     double r = 0.0;
     for (int b = 0; b < 3; ++b) r += (s->nh - 0.5) * s->g.dv[b];
@@ -178,8 +188,16 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         s->cfg.xcd_group = 64;
         s->cfg.nt_store = 1;
     }
-    s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
-    s->has_wall = m->n_faces[DVM_FACE_WALL] > 0;
+    if (m->device_tables) {
+        // no solid leaves: domain faces are the only INFLOW / WALL faces
+        for (int f = 0; f < 6; ++f) {
+            s->has_inflow |= m->bc[f] == DVM_BC_INFLOW;
+            s->has_wall |= m->bc[f] == DVM_BC_WALL;
+        }
+    } else {
+        s->has_inflow = m->n_faces[DVM_FACE_INFLOW] > 0;
+        s->has_wall = m->n_faces[DVM_FACE_WALL] > 0;
+    }
     const size_t fs = fp64 ? 8 : 4;
     s->f_bytes = align256(size_t(s->n) * size_t(s->nv) * fs);
     s->mom_bytes = align256(size_t(5) * size_t(s->n) * 8);
@@ -214,8 +232,8 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
              align256(size_t(s->n) * kFaceRecord * 8);
     // selection list: regular cells (no FINER or WALL face) first, then the rest
     s->off_sel = o;  o += align256(size_t(s->n) * 4);
-    s->sel_host.reserve(size_t(s->n));
-    for (int pass = 0; pass < 2; ++pass)
+    if (!m->device_tables) s->sel_host.reserve(size_t(s->n));
+    for (int pass = 0; pass < 2 && !m->device_tables; ++pass)
         for (int64_t c = 0; c < s->n; ++c) {
             const DevCell &d = m->table[size_t(c)];
             bool irregular = false;
@@ -258,6 +276,7 @@ int dvm_bind(dvm_solver *s, void *f_a, void *f_b, double *moments, void *tables,
     s->tables = static_cast<DevCell *>(tables);
     s->ws = static_cast<char *>(ws);
     s->uploaded = false;
+    s->tables_pending = false;
     s->steps = 0;
     return DVM_OK;
 }
@@ -266,13 +285,20 @@ int dvm_upload(dvm_solver *s, void *stream) {
     clear_error();
     if (!s || !s->ws) return fail(DVM_ERR_WORKSPACE, "solver not bound");
     hipStream_t st = S(stream);
-    hipError_t e = hipMemcpyAsync(s->tables, s->m->table.data(), s->m->table.size() * sizeof(DevCell),
-                                  hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    const bool dev_tab = s->m->device_tables;
+    hipError_t e = hipSuccess;
+    if (!dev_tab) {
+        e = hipMemcpyAsync(s->tables, s->m->table.data(), s->m->table.size() * sizeof(DevCell),
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    }
     e = hipMemsetAsync(s->ws, 0, s->ws_bytes, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(ws)");
-    e = hipMemcpyAsync(s->ws + s->off_sel, s->sel_host.data(), s->sel_host.size() * 4, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(selection)");
+    if (!dev_tab) {
+        e = hipMemcpyAsync(s->ws + s->off_sel, s->sel_host.data(), s->sel_host.size() * 4, hipMemcpyHostToDevice,
+                           st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(selection)");
+    }
     InitArgs a{};
     a.prim = nullptr;
     a.n = 1;
@@ -313,7 +339,9 @@ int dvm_upload(dvm_solver *s, void *stream) {
     // the host table must stay valid until the copy has been consumed
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    s->uploaded = true;
+    // a device-table mesh is ready once dvm_adapt_tables has built its tables
+    s->uploaded = !dev_tab;
+    s->tables_pending = dev_tab;
     return DVM_OK;
 }
 

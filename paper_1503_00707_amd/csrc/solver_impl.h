@@ -51,6 +51,7 @@ struct dvm_solver {
     dvm::DevCell *tables = nullptr;
     char *ws = nullptr;
     bool uploaded = false;
+    bool tables_pending = false;  // uploaded except the face tables of a device-table mesh
     int64_t steps = 0;
     bool has_inflow = false, has_wall = false;
     // deferred-collision engine
@@ -108,6 +109,9 @@ hipError_t solver_make_plain(dvm_solver *s, hipStream_t st);
 // Kernel arguments of one fused step of size dt (f_in / f_out left NULL).
 StepArgs solver_step_args(const dvm_solver *s, double dt);
 double solver_max_speed_sum(const dvm_solver *s);
+// f[cur] was replaced from outside the step (a remap): records, hybrid masks
+// and the moments buffer describe the new state
+hipError_t solver_state_replaced(dvm_solver *s, hipStream_t st);
 // every cell kinetic again (a fresh state); no-op without the hybrid workspace
 hipError_t solver_reset_hybrid(dvm_solver *s, hipStream_t st);
 // fluid cells of the last hybrid step: out[5][n] := their conserved moments

@@ -34,7 +34,8 @@ EXPORTED = [
     "dvm_mlp_buffers", "dvm_destroy_mlp", "dvm_sensor", "dvm_hybrid_step",
     "dvm_tune", "dvm_save", "dvm_load", "dvm_tune_cache_get", "dvm_tune_cache_put",
     "dvm_mlp_gradient_noalloc", "dvm_korobov_generator", "dvm_korobov_tables",
-    "dvm_batch_branches", "dvm_lbm_create", "dvm_lbm_buffer_sizes", "dvm_lbm_bind", "dvm_lbm_upload", "dvm_lbm_init", "dvm_lbm_dt",
+    "dvm_batch_branches", "dvm_adapt_workspace_bytes", "dvm_adapt_leaves", "dvm_adapt_mesh", "dvm_adapt_tables", "dvm_adapt_remap",
+    "dvm_lbm_create", "dvm_lbm_buffer_sizes", "dvm_lbm_bind", "dvm_lbm_upload", "dvm_lbm_init", "dvm_lbm_dt",
     "dvm_lbm_step", "dvm_lbm_moments", "dvm_lbm_check", "dvm_lbm_get_f", "dvm_lbm_set_f", "dvm_lbm_current_f",
     "dvm_destroy_lbm",
 ]
@@ -122,6 +123,11 @@ def lib():
         L.dvm_tune.argtypes = [P, C.c_char_p, C.c_int32, C.POINTER(C.c_int32), P]
         L.dvm_save.argtypes = [P, P, C.c_char_p, P]
         L.dvm_load.argtypes = [P, P, C.c_char_p, P]
+        L.dvm_adapt_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.dvm_adapt_leaves.argtypes = [P, P, C.c_int64, P, P, C.POINTER(C.c_int64), P, C.c_size_t, P]
+        L.dvm_adapt_mesh.argtypes = [P, P, P, C.c_int64, C.POINTER(P), P]
+        L.dvm_adapt_tables.argtypes = [P, P, P, P, C.c_size_t, P]
+        L.dvm_adapt_remap.argtypes = [P, P, P, C.c_size_t, P]
         L.dvm_batch_branches.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_lbm_create.argtypes = [P, C.POINTER(LbmParams), C.POINTER(P)]
         L.dvm_lbm_buffer_sizes.argtypes = [P, C.POINTER(Sizes)]
@@ -208,8 +214,19 @@ class Mesh:
         _check(lib().dvm_create_mesh(C.byref(d), C.byref(h)), "dvm_create_mesh")
         self.h = h
         self.forest = forest
+        self._info()
+
+    @classmethod
+    def wrap(cls, h, forest):
+        """a Mesh object owning the handle `h` (e.g. from dvm_adapt_mesh)"""
+        self = cls.__new__(cls)
+        self.h, self.forest = h, forest
+        self._info()
+        return self
+
+    def _info(self):
         info = MeshInfo()
-        _check(lib().dvm_mesh_info(h, C.byref(info)), "dvm_mesh_info")
+        _check(lib().dvm_mesh_info(self.h, C.byref(info)), "dvm_mesh_info")
         self.n_leaves, self.n_cells = int(info.n_leaves), int(info.n_cells)
         self.h_min, self.max_level = float(info.h_min), int(info.max_level)
         self.n_faces = list(info.n_faces)
@@ -441,6 +458,39 @@ class Solver:
                 self.h = None
         except Exception:  # interpreter shutdown
             pass
+
+
+def adapt(solver, flags, cap=None):
+    """On-device adaptation of a solver's mesh (dvm_adapt_*): flags (int8 per
+    cell: +1 refine, -1 coarsen a complete sibling set, 0 keep) -> the new
+    2:1-balanced leaf list (device), a solver on it with the same parameters,
+    its face tables built on the device and its state remapped from `solver`.
+    Returns (forest, mesh, solver)."""
+    import dataclasses
+    import torch
+    n = solver.n
+    cap = 8 * n if cap is None else int(cap)
+    fl = torch.as_tensor(np.ascontiguousarray(flags, np.int8)).to("cuda")
+    nb = C.c_size_t(0)
+    _check(lib().dvm_adapt_workspace_bytes(cap + n, C.byref(nb)), "dvm_adapt_workspace_bytes")
+    ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device="cuda")
+    lev = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    ijk = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+    n_out = C.c_int64(0)
+    _check(lib().dvm_adapt_leaves(solver.h, fl.data_ptr(), cap, lev.data_ptr(), ijk.data_ptr(), C.byref(n_out),
+                                  ws.data_ptr(), nb.value, solver.stream()), "dvm_adapt_leaves")
+    m = n_out.value
+    mh = C.c_void_p()
+    _check(lib().dvm_adapt_mesh(solver.mesh.h, lev.data_ptr(), ijk.data_ptr(), m, C.byref(mh), solver.stream()),
+           "dvm_adapt_mesh")
+    forest = dataclasses.replace(solver.mesh.forest, level=lev[:m].cpu().numpy(), ijk=ijk[:m].cpu().numpy())
+    mesh = Mesh.wrap(mh, forest)
+    new = Solver(mesh, solver.params)
+    _check(lib().dvm_adapt_tables(new.h, lev.data_ptr(), ijk.data_ptr(), ws.data_ptr(), nb.value, new.stream()),
+           "dvm_adapt_tables")
+    mesh._info()  # face counts, known once the tables exist
+    _check(lib().dvm_adapt_remap(solver.h, new.h, ws.data_ptr(), nb.value, new.stream()), "dvm_adapt_remap")
+    return forest, mesh, new
 
 
 class LBM:
