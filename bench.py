@@ -487,6 +487,7 @@ def gpu_hybrid():
     same flow is the judge of the error, and the Kn_GLL criterion calibrated
     against the same bar runs beside the network.  Needs the committed
     trained sensor."""
+    from paper_1503_00707_amd import dvm as D
     from paper_1503_00707_amd import sensor_train as T
     if not os.path.exists(T.TRAINED):
         return None
@@ -505,6 +506,9 @@ def gpu_hybrid():
         r["cvu_per_s_hybrid"] = n_cells * n_v / (r["ms_hybrid"] / 1e3)
         r["cvu_per_s_plain"] = n_cells * n_v / (r["ms_full"] / 1e3)
         r["kn_gll"] = {k: kn[k] for k in ("error", "kinetic_fraction", "ms_hybrid", "speedup")}
+        # the same run with closed-form (erf) half-range fluxes between fluid cells
+        cf = T.evaluate(net, tau=tau, level=level, nv=nv, vmax=vmax, graph=True, fluid_flux=D.FLUX_CLOSED)
+        r["closed_form_fluid_flux"] = {k: cf[k] for k in ("error", "kinetic_fraction", "ms_hybrid", "speedup")}
         out[name] = r
         log(f"[bench] hybrid {name}: {r}")
     return out

@@ -83,6 +83,11 @@ extern "C" {
 #define DVM_COLL_KOROBOV 3      /* f' = f* + dt/Kn I(f*), I the hard-sphere Boltzmann integral on
                                    Korobov lattice nodes with the correction of eq. (6)
                                    (section 3.2); Kn = tau_or_kn; N = 4, 8 or 12 */
+#define DVM_FLUX_GRID 0         /* hybrid fluid-fluid faces: half-range sums of Mt(U) over the
+                                   discrete velocity set (exactly what a kinetic neighbour sees) */
+#define DVM_FLUX_CLOSED 1       /* hybrid fluid-fluid faces: the continuous half-range integrals
+                                   of the Maxwellian of U (erf / exp closed form, kinetic
+                                   flux-vector splitting); kinetic-fluid faces keep the sums */
 #define DVM_TAU_CONST 0         /* tau = tau_or_kn */
 #define DVM_TAU_HS 1            /* tau = Kn T^(-1/2) / rho (hard sphere) */
 
@@ -123,6 +128,7 @@ typedef struct {
     int32_t hybrid;           /* 1: workspace for dvm_hybrid_step (masks, flux sums) */
     int32_t korobov_p;        /* DVM_COLL_KOROBOV: lattice points per velocity node (a prime) */
     int32_t korobov_a;        /* DVM_COLL_KOROBOV: lattice generator; 0: Korobov's optimal one */
+    int32_t fluid_flux;       /* DVM_FLUX_*: fluxes between two fluid cells of dvm_hybrid_step */
 } dvm_params;
 
 typedef struct {
@@ -449,7 +455,11 @@ void dvm_destroy_batch(dvm_batch *b);
  * half-range fluxes of the discrete velocity set, U' = U - dt/h
  * sum_faces (H_out(Mt(U)) + H_in(neighbour)), the neighbour's f when it is
  * kinetic or Mt(U_nb) when it is fluid (section 2-3 of the paper: kinetic and
- * continuum cells on one mesh).  A cell that becomes kinetic starts from
+ * continuum cells on one mesh).  With params.fluid_flux = DVM_FLUX_CLOSED a
+ * face between two fluid cells takes instead the continuous half-range
+ * integrals of both sides' Maxwellians (the same on both sides of the face,
+ * so fluid cells still conserve among themselves); faces next to a kinetic
+ * cell keep the discrete sums, which that cell's transport sees.  A cell that becomes kinetic starts from
  * Mt(U); one that becomes fluid keeps the moments of its f.  Cells touching
  * a non-periodic domain face stay kinetic.  Needs params.hybrid = 1, the
  * fused engine and first order (DVM_ERR_UNSUPPORTED otherwise).  With every

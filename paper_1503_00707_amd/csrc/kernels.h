@@ -102,8 +102,10 @@ struct HybArgsPub {
     uint8_t *rows;
     double *flux;
     double *face;
+    int32_t closed;  // fluid-fluid faces: continuous half-range integrals
+    int32_t pad;
 };
-constexpr int kMlpParams = 4949, kMlpWeights = 4929, kMlpRecord = 331, kFluxRecord = 66, kFaceRecord = 30;
+constexpr int kMlpParams = 4949, kMlpWeights = 4929, kMlpRecord = 331, kFluxRecord = 71, kFaceRecord = 30;
 hipError_t launch_features(const SensorArgsPub &a, float *x, hipStream_t st);
 hipError_t launch_labels(bool fp64, const void *f, float *r, int64_t n, const VelGrid &g, hipStream_t st);
 hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, int mode, float *z, hipStream_t st);

@@ -190,7 +190,8 @@ int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double 
     hipError_t e = solver_make_plain(s, st);
     if (e == hipSuccess) e = launch_mask_eff(mask, hyb_mask(s), s->tables, s->n, st);
     if (e != hipSuccess) return hip_fail(e, "hybrid mask");
-    const HybArgsPub h{hyb_mask(s), hyb_prev(s), hyb_rows(s), hyb_flux(s), hyb_face(s)};
+    const HybArgsPub h{hyb_mask(s), hyb_prev(s), hyb_rows(s), hyb_flux(s), hyb_face(s),
+                       s->p.fluid_flux == DVM_FLUX_CLOSED ? 1 : 0, 0};
     for (int it = 0; it < n_steps; ++it) {
         StepArgs a = solver_step_args(s, dt);
         a.f_in = s->f[s->cur];

@@ -467,7 +467,8 @@ __global__ __launch_bounds__(256) void k_norm_stats(const float *x, int64_t n, f
 // hybrid step
 // ---------------------------------------------------------------------------
 
-constexpr int kFluxRec = 66;  // per axis: full A[3], B[3]; + half A[4], B[4]; - half A[4], B[4]
+// per axis: full A[3], B[3]; + half A[4], B[4]; - half A[4], B[4]; then rho, u[3], T
+constexpr int kFluxRec = 71;
 
 struct HybArgs {
     const uint8_t *mask;  // effective mask (1 kinetic)
@@ -475,6 +476,8 @@ struct HybArgs {
     uint8_t *rows;        // 1: write Mt(U) into the state buffer before the step
     double *flux;         // [n][kFluxRec] separable sums of fluid cells' Maxwellians
     double *face;         // [n][6][5] outgoing half-range fluxes of kinetic cells next to fluid ones
+    int32_t closed;       // fluid-fluid faces: continuous half-range integrals (erf form)
+    int32_t pad;
 };
 
 // mask | (cell touches a non-periodic domain face): those cells stay kinetic
@@ -556,6 +559,15 @@ __global__ __launch_bounds__(256) void k_fluid_state(StepArgs a, HybArgs h) {
     }
     const int nh = a.g.nh, N = 2 * nh;
     double *R = h.flux + c * kFluxRec;
+    {
+        // the primitive state of U itself (the closed-form fluxes)
+        const double rho = U[0], v0 = U[1] / rho, v1 = U[2] / rho, v2 = U[3] / rho;
+        R[66] = rho;
+        R[67] = v0;
+        R[68] = v1;
+        R[69] = v2;
+        R[70] = (2.0 * U[4] / rho - ((v0 * v0 + v1 * v1) + v2 * v2)) / 3.0;
+    }
     for (int b = 0; b < 3; ++b) {
         double acc[22];
         for (int t = 0; t < 22; ++t) acc[t] = 0.0;
@@ -728,6 +740,36 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     }
 }
 
+// Half-range flux of the continuous Maxwellian of (rho, u, T) = P[0..4]
+// through a face with normal e_b: the integral over xi_b > 0 (pos) or < 0 of
+// xi_b (1, xi, |xi|^2 / 2) M.  With xi_b = u_b + sqrt(T) t, t standard
+// normal, the half-space is t > -s (pos) or t < -s, s = u_b / sqrt(T); its
+// probability is q = erfc(-+s / sqrt 2) / 2 and the truncated moments of t
+// follow from phi(s) = exp(-s^2/2) / sqrt(2 pi): E[t] = +-phi,
+// E[t^2] = q -+ s phi, E[t^3] = +-(s^2 + 2) phi.  The transverse axes are
+// full Gaussians (mean u_a, variance T).
+__device__ __forceinline__ void closed_flux(const double *P, int b, bool pos, double out[5]) {
+    const double rho = P[0], T = P[4], sd = sqrt(T);
+    const double ub = P[1 + b], s = ub / sd;
+    const double sg = pos ? 1.0 : -1.0;
+    const double q = 0.5 * erfc(-sg * s * 0.70710678118654752440);
+    const double ph = exp(-0.5 * s * s) * 0.39894228040143267794;
+    const double m1 = ub * q + sg * sd * ph;
+    const double m2 = (ub * ub + T) * q + sg * ub * sd * ph;
+    const double m3 = (ub * ub + 3.0 * T) * ub * q + sg * (ub * ub + 2.0 * T) * sd * ph;
+    double tr = 0.0;
+    for (int x = 0; x < 3; ++x) {
+        if (x == b) {
+            out[1 + x] = rho * m2;
+        } else {
+            out[1 + x] = rho * P[1 + x] * m1;
+            tr += P[1 + x] * P[1 + x] + T;
+        }
+    }
+    out[0] = rho * m1;
+    out[4] = 0.5 * rho * (m3 + m1 * tr);
+}
+
 // Fluid cells, one thread each: U' = U - dt/h sum_faces (H_out + H_in).
 __global__ __launch_bounds__(256) void k_fluid_update(StepArgs a, HybArgs h) {
     const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x, n = a.n_cells;
@@ -743,6 +785,25 @@ __global__ __launch_bounds__(256) void k_fluid_update(StepArgs a, HybArgs h) {
         double hout[5];
         sep_flux(h.flux + c * kFluxRec, b, side ? 6 : 14, w, hout);
         const int nk = ty == DVM_FACE_FINER ? 4 : 1;
+        if (h.closed) {
+            // per neighbour: closed-form fluxes on both sides of a fluid-fluid
+            // face, the discrete ones where the neighbour is kinetic
+            double cout[5], s[5] = {0, 0, 0, 0, 0};
+            closed_flux(h.flux + c * kFluxRec + 66, b, side == 1, cout);
+            for (int k = 0; k < nk; ++k) {
+                const int64_t nb = cell.nbr[f][k];
+                double t[5];
+                if (h.mask[nb] == 0) {
+                    closed_flux(h.flux + nb * kFluxRec + 66, b, side == 0, t);
+                    for (int x = 0; x < 5; ++x) s[x] += cout[x] + t[x];
+                } else {
+                    const double *q = h.face + (nb * 6 + (f ^ 1)) * 5;
+                    for (int x = 0; x < 5; ++x) s[x] += hout[x] + q[x];
+                }
+            }
+            for (int x = 0; x < 5; ++x) acc[x] += sg * (s[x] / double(nk));
+            continue;
+        }
         double hin[5] = {0, 0, 0, 0, 0};
         for (int k = 0; k < nk; ++k) {
             const int64_t nb = cell.nbr[f][k];

@@ -133,6 +133,7 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     if (p->scheme != DVM_SCHEME_UPWIND1 && p->scheme != DVM_SCHEME_MUSCL) return fail(DVM_ERR_ARG, "bad scheme");
     if (p->collision < DVM_COLL_EXP || p->collision > DVM_COLL_KOROBOV) return fail(DVM_ERR_ARG, "bad collision mode");
     if (p->tau_mode != DVM_TAU_CONST && p->tau_mode != DVM_TAU_HS) return fail(DVM_ERR_ARG, "bad tau mode");
+    if (p->fluid_flux != DVM_FLUX_GRID && p->fluid_flux != DVM_FLUX_CLOSED) return fail(DVM_ERR_ARG, "bad fluid_flux");
     if (p->collision != DVM_COLL_OFF && !(p->tau_or_kn > 0)) return fail(DVM_ERR_ARG, "tau_or_kn must be > 0");
     const bool fp64 = p->precision == DVM_PREC_FP64;
     const int nh = p->nv / 2;

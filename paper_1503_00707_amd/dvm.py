@@ -21,6 +21,7 @@ PREC_FP64, PREC_FP32 = 0, 1
 SCHEME_UPWIND1, SCHEME_MUSCL = 0, 1
 COLL_EXP, COLL_EULER, COLL_OFF, COLL_KOROBOV = 0, 1, 2, 3
 TAU_CONST, TAU_HS = 0, 1
+FLUX_GRID, FLUX_CLOSED = 0, 1
 
 EXPORTED = [
     "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
@@ -62,7 +63,8 @@ class Params(C.Structure):
     _fields_ = [("nv", C.c_int32), ("vmax", C.c_double * 3), ("precision", C.c_int32), ("scheme", C.c_int32),
                 ("collision", C.c_int32), ("tau_mode", C.c_int32), ("tau_or_kn", C.c_double),
                 ("inflow", C.c_double * 5), ("t_wall", C.c_double), ("check_every", C.c_int32),
-                ("hybrid", C.c_int32), ("korobov_p", C.c_int32), ("korobov_a", C.c_int32)]
+                ("hybrid", C.c_int32), ("korobov_p", C.c_int32), ("korobov_a", C.c_int32),
+                ("fluid_flux", C.c_int32)]
 
 
 class LbmParams(C.Structure):
@@ -252,7 +254,7 @@ class Mesh:
 
 def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=COLL_EXP, tau_mode=TAU_CONST,
                 tau_or_kn=0.1, inflow=(1.0, 0.0, 0.0, 0.0, 1.0), t_wall=1.0, check_every=0,
-                hybrid=False, korobov_p=0, korobov_a=0) -> Params:
+                hybrid=False, korobov_p=0, korobov_a=0, fluid_flux=0) -> Params:
     p = Params()
     p.nv = int(nv)
     vm = (vmax,) * 3 if np.isscalar(vmax) else tuple(vmax)
@@ -266,6 +268,7 @@ def make_params(nv, vmax, precision=PREC_FP32, scheme=SCHEME_UPWIND1, collision=
     p.check_every = int(check_every)
     p.hybrid = int(bool(hybrid))
     p.korobov_p, p.korobov_a = int(korobov_p), int(korobov_a)
+    p.fluid_flux = int(fluid_flux)
     return p
 
 

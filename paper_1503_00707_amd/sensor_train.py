@@ -151,18 +151,19 @@ class PlainGraph:
 
 
 def evaluate(net, kappa=None, fields="sine_rho", field_args=None, tau=0.1, steps=20, precision=D.PREC_FP32,
-             level=4, nv=NV, vmax=VMAX, graph=False):
+             level=4, nv=NV, vmax=VMAX, graph=False, fluid_flux=D.FLUX_GRID):
     """hybrid (sensor every step) vs full DVM on one flow of the periodic
     unit cube at 2^level cells per side (4: the C1 mesh): dict with the moment
     error, mean kinetic fraction, and both step times.  graph: both sides
-    replay two-step HIP graphs (steps must be even)."""
+    replay two-step HIP graphs (steps must be even).  fluid_flux: the
+    hybrid's fluxes between fluid cells (discrete sums or closed form)."""
     import torch
     field_args = {"a": 0.1} if field_args is None else field_args
     forest = c1_mesh(level)
     mesh = D.Mesh(forest)
     t = mesh.tables()
     prim = I.fields(fields, I.leaf_centres(forest)[t["input"]], **field_args)
-    p = D.make_params(nv, vmax, precision=precision, tau_or_kn=tau, hybrid=True)
+    p = D.make_params(nv, vmax, precision=precision, tau_or_kn=tau, hybrid=True, fluid_flux=fluid_flux)
     full = D.Solver(mesh, p)
     full.init_maxwellian(prim)
     hyb = D.Solver(mesh, p)

@@ -22,7 +22,7 @@ def _case(seed=3, tau=0.05, tau_mode=I.TAU_CONST):
     return f
 
 
-def _pair(f, steps, prec=D.PREC_FP64, tau=0.05, tau_mode=I.TAU_CONST, hybrid=False, fseed=31):
+def _pair(f, steps, prec=D.PREC_FP64, tau=0.05, tau_mode=I.TAU_CONST, hybrid=False, fseed=31, fluid_flux=0):
     """the same seeded flow advanced by the oracle and by the library"""
     om = O.Mesh(f)
     ot = om.tables()
@@ -35,7 +35,8 @@ def _pair(f, steps, prec=D.PREC_FP64, tau=0.05, tau_mode=I.TAU_CONST, hybrid=Fal
         os_.step(dt, steps)
     dm = D.Mesh(f)
     dt_ = dm.tables()
-    p = D.make_params(8, 4.5, precision=prec, tau_mode=tau_mode, tau_or_kn=tau, hybrid=hybrid)
+    p = D.make_params(8, 4.5, precision=prec, tau_mode=tau_mode, tau_or_kn=tau, hybrid=hybrid,
+                      fluid_flux=fluid_flux)
     s = D.Solver(dm, p)
     s.init_maxwellian(I.fields("sines", I.leaf_centres(f)[dt_["input"]], seed=fseed))
     if steps:
@@ -153,6 +154,38 @@ def test_hybrid_all_kinetic_is_plain_step_bitwise():
     torch.cuda.synchronize()
     assert np.array_equal(s1.f_canonical().cpu().numpy(), s2.f_canonical().cpu().numpy())
     assert np.array_equal(s1.mom.cpu().numpy(), s2.mom.cpu().numpy())
+
+
+@pytest.mark.parametrize("frac,seed", [(0.2, 8), (0.6, 5), (0.0, 3)])
+def test_hybrid_closed_form_fluid_fluxes_match_oracle_fp64(frac, seed):
+    """fluid_flux = DVM_FLUX_CLOSED: faces between two fluid cells take the
+    continuous half-range Maxwellian fluxes (erf form), the others the
+    discrete sums; against the oracle's Hybrid(flux="closed"), FP64, level
+    jumps, mixed and all-fluid masks; global conservation to 1e-13"""
+    import torch
+    f = _case(seed=seed)
+    om, ot, op, os_, dm, s, dt = _pair(f, 0, hybrid=True, fluid_flux=D.FLUX_CLOSED)
+    rng = np.random.default_rng(seed)
+    h = S.Hybrid(os_, op, NV, VLO, VHI, flux="closed")
+    vol = (f.h0 / 2.0 ** ot["level"].astype(float)) ** 3
+    tot0 = (h.U * vol).sum(1)
+    for rep in range(2):
+        mask = rng.random(s.n) < frac
+        h.set_mask(mask)
+        for _ in range(2):
+            h.step(dt)
+        s.hybrid_step(mask.astype(np.uint8), n=2, dt=dt)
+    torch.cuda.synchronize()
+    Ug = s.mom.cpu().numpy()
+    scale = np.abs(h.U).max(axis=1)
+    assert np.all(np.abs(Ug - h.U).max(axis=1) <= 1e-12 * scale)
+    kin = h.kinetic
+    if kin.any():
+        fg = s.f_canonical().cpu().numpy()
+        assert np.abs(fg[kin] - h.f[kin]).max() <= 1e-12 * np.abs(h.f[kin]).max()
+    tot = (Ug * vol).sum(1)
+    sc = np.array([tot0[0]] * 4 + [tot0[4]])
+    assert np.all(np.abs(tot - tot0) <= 1e-13 * sc)
 
 
 @pytest.mark.parametrize("frac", [0.3, 0.7])
