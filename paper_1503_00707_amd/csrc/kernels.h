@@ -127,7 +127,8 @@ hipError_t launch_fluid_moments(const uint8_t *mask, const double *mom, double *
 // Boltzmann collision integral on Korobov nodes (korobov.hip / korobov.cpp).
 struct KorArgs {
     void *f;                 // [n_cells][NV] post-transport state, updated in place
-    const uint64_t *table;   // [p][NV] entries j | l << 16 | m << 32 (internal indices; 0xFFFF: no gain)
+    const uint64_t *table;   // [p][NV] entries j | l << 16 | m << 32 | n << 48 (internal indices; 0xFFFF:
+                             // no gain; n = |k_j - k_i|^2 in node units)
     int64_t n_cells;
     int p;
     double w0;               // V_box / p

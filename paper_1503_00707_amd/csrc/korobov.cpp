@@ -149,7 +149,11 @@ void korobov_device_table(int nh, const std::vector<int32_t> &J, const std::vect
             const uint64_t j = uint64_t(to_int[size_t(J[e])]);
             const uint64_t l = L[e] < 0 ? 0xFFFFu : uint64_t(to_int[size_t(L[e])]);
             const uint64_t m = M[e] < 0 ? 0xFFFFu : uint64_t(to_int[size_t(M[e])]);
-            out[size_t(k * nv + to_int[size_t(i)])] = j | (l << 16) | (m << 32);
+            // |k_j - k_i|^2 in node units: |xi_j - xi_i| = dv sqrt(n) on the cubic grid
+            const int64_t a = J[e], dx = a / (n * n) - i / (n * n), dy = (a / n) % n - (i / n) % n,
+                          dz = a % n - i % n;
+            const uint64_t g2 = uint64_t(dx * dx + dy * dy + dz * dz);
+            out[size_t(k * nv + to_int[size_t(i)])] = j | (l << 16) | (m << 32) | (g2 << 48);
         }
 }
 

@@ -5,12 +5,15 @@
 //   I_i = -f_i P_i B_i + C_i     (eq. 6, conservative correction)
 //   f'_i = f_i + (dt / Kn) I_i,  W = V_box |xi_j - xi_i| / p.
 // The trial tables are the same for every cell.  A workgroup takes a tile
-// of CELLS cells: their rows sit in LDS (gathers at the table's indices are
-// LDS reads), each table entry is read once per tile and applied to all of
-// its cells, and B, C stay in LDS for the correction.  The five coefficients
-// of P solve the conservation system in the scaled basis
-// (1, xi/v, |xi|^2/v^2), v = the grid's half width (the span of eq. 6's
-// (1, xi, |xi|^2): the same P), assembled from FP64 workgroup sums.
+// of CELLS cells whose rows sit in LDS node-major ([node][cell]), so the
+// gather of one node for all cells of the tile is one contiguous vector
+// read; each thread owns NV / T velocity nodes and keeps their B and C for
+// every cell of the tile in registers.  A table entry (read once per tile)
+// carries the three node indices and n = |k_j - k_i|^2 in grid units, so
+// W = w0 dv sqrt(n) is a lookup in a small LDS table.  The five coefficients
+// of P solve the conservation system in the scaled basis (1, xi/v,
+// |xi|^2/v^2), v = the grid's half width (the span of eq. 6's (1, xi,
+// |xi|^2): the same P), assembled from FP64 workgroup sums.
 // The paper's own kernel runs one thread block per velocity node over all
 // cells, f stored velocity-major and transposed for the correction; here the
 // tables stream through L2 once per tile and f is never transposed.
@@ -63,93 +66,119 @@ __device__ inline bool solve5(double A[5][5], double r[5], double x[5]) {
     return true;
 }
 
-template <typename F, int NH, int CELLS>
-__global__ __launch_bounds__(256) void k_korobov(KorArgs a) {
-    constexpr int NV = 8 * NH * NH * NH, T = 256;
-    __shared__ F fs[CELLS][NV];
-    __shared__ double Bs[CELLS][NV], Cs[CELLS][NV];
-    __shared__ double red[(T / 64) * 20];
+template <typename F, int NH, int T, int CELLS, int WPE>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_korobov(KorArgs a) {
+    constexpr int NV = 8 * NH * NH * NH, R = NV / T, NW = 3 * (2 * NH - 1) * (2 * NH - 1) + 1;
+    static_assert(NV % T == 0 && T % 64 == 0, "whole nodes per thread, whole waves");
+    // a node's row of the tile, padded by 16 bytes so that rows start on
+    // 16 different bank groups (random rows are gathered every trial)
+    constexpr int RS = CELLS + 16 / int(sizeof(F));
+    __shared__ __align__(16) F fs[NV * RS];
+    __shared__ double Wn[NW];
+    __shared__ double red[(T / 64) * CELLS * 20];
     __shared__ double dco[CELLS][5];
     F *f = static_cast<F *>(a.f);
     const int64_t c0 = int64_t(blockIdx.x) * CELLS;
     const int nc = int(min(int64_t(CELLS), a.n_cells - c0));
-    for (int c = 0; c < nc; ++c)
-        for (int v = threadIdx.x; v < NV; v += T) fs[c][v] = f[(c0 + c) * NV + v];
+    for (int c = 0; c < CELLS; ++c)
+        for (int v = threadIdx.x; v < NV; v += T) fs[v * RS + c] = c < nc ? f[(c0 + c) * NV + v] : F(0);
+    const double wd = a.w0 * a.g.dv[0];
+    for (int q = threadIdx.x; q < NW; q += T) Wn[q] = wd * sqrt(double(q));
     __syncthreads();
     // eqs. 4 and 5: each table entry once per tile, applied to every cell of it
-    for (int i = threadIdx.x; i < NV; i += T) {
-        double xi[3];
-        node_velocity<NH>(i, a.g, xi);
-        double b[CELLS], cc[CELLS];
+    double b[R][CELLS], cc[R][CELLS];
 #pragma unroll
-        for (int c = 0; c < CELLS; ++c) b[c] = cc[c] = 0.0;
-        for (int k = 0; k < a.p; ++k) {
-            const uint64_t e = a.table[int64_t(k) * NV + i];
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < CELLS; ++c) b[r][c] = cc[r][c] = 0.0;
+    const uint64_t *tab = a.table + threadIdx.x;
+    for (int k = 0; k < a.p; ++k, tab += NV) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t e = tab[r * T];
             const int j = int(e & 0xFFFFu), l = int((e >> 16) & 0xFFFFu), m = int((e >> 32) & 0xFFFFu);
-            double xs[3];
-            node_velocity<NH>(j, a.g, xs);
-            const double gx = xs[0] - xi[0], gy = xs[1] - xi[1], gz = xs[2] - xi[2];
-            const double W = a.w0 * sqrt(gx * gx + gy * gy + gz * gz);
+            const double W = Wn[int(e >> 48)];
+            F fj[CELLS];
+            __builtin_memcpy(fj, fs + j * RS, sizeof fj);
+#pragma unroll
+            for (int c = 0; c < CELLS; ++c) b[r][c] += W * double(fj[c]);
             if (l != 0xFFFF) {
+                F fl[CELLS], fm[CELLS];
+                __builtin_memcpy(fl, fs + l * RS, sizeof fl);
+                __builtin_memcpy(fm, fs + m * RS, sizeof fm);
 #pragma unroll
-                for (int c = 0; c < CELLS; ++c) {
-                    b[c] += W * double(fs[c][j]);
-                    cc[c] += W * double(fs[c][l]) * double(fs[c][m]);
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < CELLS; ++c) b[c] += W * double(fs[c][j]);
+                for (int c = 0; c < CELLS; ++c) cc[r][c] += W * double(fl[c]) * double(fm[c]);
             }
         }
-#pragma unroll
-        for (int c = 0; c < CELLS; ++c) {
-            Bs[c][i] = b[c];
-            Cs[c][i] = cc[c];
-        }
     }
-    __syncthreads();
     // eq. 6: per cell the 5x5 conservation system in the scaled basis
     const double iv = 1.0 / a.vmax;
-    for (int c = 0; c < nc; ++c) {
+    double psi[R][5];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double xi[3];
+        node_velocity<NH>(int(threadIdx.x) + r * T, a.g, xi);
+        psi[r][0] = 1.0;
+        psi[r][1] = xi[0] * iv;
+        psi[r][2] = xi[1] * iv;
+        psi[r][3] = xi[2] * iv;
+        psi[r][4] = (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) * iv * iv;
+    }
+    // per cell 20 sums (15 of the symmetric matrix, 5 of the right side):
+    // wave sums into LDS, then one barrier, the wave totals, and one thread
+    // per cell solves its system
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < CELLS; ++c) {
         double s[20];
 #pragma unroll
         for (int q = 0; q < 20; ++q) s[q] = 0.0;
-        for (int i = threadIdx.x; i < NV; i += T) {
-            double xi[3];
-            node_velocity<NH>(i, a.g, xi);
-            const double psi[5] = {1.0, xi[0] * iv, xi[1] * iv, xi[2] * iv,
-                                   (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) * iv * iv};
-            const double fb = double(fs[c][i]) * Bs[c][i];
-            const double rr = Cs[c][i] - fb;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double fb = double(fs[(int(threadIdx.x) + r * T) * RS + c]) * b[r][c];
+            const double rr = cc[r][c] - fb;
             int q = 0;
 #pragma unroll
             for (int x = 0; x < 5; ++x)
 #pragma unroll
-                for (int y = x; y < 5; ++y) s[q++] += psi[x] * psi[y] * fb;
+                for (int y = x; y < 5; ++y) s[q++] += psi[r][x] * psi[r][y] * fb;
 #pragma unroll
-            for (int x = 0; x < 5; ++x) s[15 + x] += psi[x] * rr;
+            for (int x = 0; x < 5; ++x) s[15 + x] += psi[r][x] * rr;
         }
-        block_sum<T, 20>(s, red);
-        if (threadIdx.x == 0) {
-            double A[5][5], r[5], d[5] = {0, 0, 0, 0, 0};
-            int q = 0;
-            for (int x = 0; x < 5; ++x)
-                for (int y = x; y < 5; ++y) A[x][y] = A[y][x] = s[q++];
-            for (int x = 0; x < 5; ++x) r[x] = s[15 + x];
-            if (!solve5(A, r, d)) *a.flag = 1;
-            for (int x = 0; x < 5; ++x) dco[c][x] = d[x];
+#pragma unroll
+        for (int q = 0; q < 20; ++q) {
+            const double t = wave_sum(s[q]);
+            if (lane == 0) red[(wid * CELLS + c) * 20 + q] = t;
         }
     }
     __syncthreads();
-    for (int c = 0; c < nc; ++c) {
+    if (threadIdx.x < CELLS && int(threadIdx.x) < nc) {
+        const int c = threadIdx.x;
+        double sm[20];
+        for (int q = 0; q < 20; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < T / 64; ++w) t += red[(w * CELLS + c) * 20 + q];
+            sm[q] = t;
+        }
+        double A[5][5], rv[5], d[5] = {0, 0, 0, 0, 0};
+        int q = 0;
+        for (int x = 0; x < 5; ++x)
+            for (int y = x; y < 5; ++y) A[x][y] = A[y][x] = sm[q++];
+        for (int x = 0; x < 5; ++x) rv[x] = sm[15 + x];
+        if (!solve5(A, rv, d)) *a.flag = 1;
+        for (int x = 0; x < 5; ++x) dco[c][x] = d[x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CELLS; ++c) {
+        if (c >= nc) break;
         const double d0 = dco[c][0], d1 = dco[c][1], d2 = dco[c][2], d3 = dco[c][3], d4 = dco[c][4];
-        for (int i = threadIdx.x; i < NV; i += T) {
-            double xi[3];
-            node_velocity<NH>(i, a.g, xi);
-            const double P = 1.0 + d0 + (d1 * xi[0] + d2 * xi[1] + d3 * xi[2]) * iv +
-                             d4 * (xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]) * iv * iv;
-            const double fv = double(fs[c][i]);
-            const double I = -fv * P * Bs[c][i] + Cs[c][i];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = int(threadIdx.x) + r * T;
+            const double P = 1.0 + d0 + (d1 * psi[r][1] + d2 * psi[r][2] + d3 * psi[r][3]) + d4 * psi[r][4];
+            const double fv = double(fs[i * RS + c]);
+            const double I = -fv * P * b[r][c] + cc[r][c];
             f[(c0 + c) * NV + i] = F(fv + a.dt_kn * I);
         }
     }
@@ -160,15 +189,15 @@ __global__ __launch_bounds__(256) void k_korobov(KorArgs a) {
 
 template <typename F>
 static hipError_t korobov_dispatch(const KorArgs &a, hipStream_t st) {
-#define DVM_KOR(NH, CELLS)                                                                         \
+#define DVM_KOR(NH, T, CELLS, W)                                                                    \
     case NH:                                                                                       \
-        hipLaunchKernelGGL((impl::k_korobov<F, NH, CELLS>), dim3(unsigned((a.n_cells + CELLS - 1) / CELLS)), \
-                           dim3(256), 0, st, a);                                                   \
+        hipLaunchKernelGGL((impl::k_korobov<F, NH, T, CELLS, W>), dim3(unsigned((a.n_cells + CELLS - 1) / CELLS)), \
+                           dim3(T), 0, st, a);                                                     \
         break;
     switch (a.g.nh) {
-        DVM_KOR(2, 16)
-        DVM_KOR(4, 4)
-        DVM_KOR(6, 1)
+        DVM_KOR(2, 64, 8, 3)
+        DVM_KOR(4, 512, 8, 4)
+        DVM_KOR(6, 576, 4, 3)
     default: return hipErrorInvalidValue;
     }
 #undef DVM_KOR
