@@ -162,6 +162,7 @@ struct LbmArgs {
     double relax;       // exp(-dt/tau) (exponential) or dt/tau (explicit Euler)
     int euler;
     int *flag;
+    int xcd_log2;       // workgroups of 256 cells go to the XCDs in runs of 2^xcd_log2
 };
 hipError_t launch_lbm_step(int q, bool fp64, const LbmArgs &a, hipStream_t st);
 hipError_t launch_lbm_moments(int q, bool fp64, const void *f, const LbmCell *cells, int64_t n, double h0,

@@ -173,6 +173,7 @@ int dvm_lbm_step(dvm_lbm *s, int32_t n_steps, double dt, double cfl, void *strea
     a.h0 = s->m->h0;
     a.euler = s->p.collision == DVM_COLL_EULER;
     a.relax = a.euler ? dt / s->p.tau : std::exp(-dt / s->p.tau);
+    a.xcd_log2 = 5;  // 8,192 consecutive cells per XCD run: their face neighbours share that XCD's L2
     a.flag = s->flag();
     for (int it = 0; it < n_steps; ++it) {
         a.f_in = s->f[s->cur];

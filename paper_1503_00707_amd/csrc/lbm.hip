@@ -45,7 +45,7 @@ __device__ __forceinline__ int face_kind(uint32_t meta, int f) { return int((met
 
 template <typename F, int Q>
 __global__ __launch_bounds__(256) void k_lbm(LbmArgs a) {
-    const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t c = int64_t(impl::remap_cell(blockIdx.x, gridDim.x, a.xcd_log2)) * 256 + threadIdx.x;
     if (c >= a.n) return;
     const F *fi = static_cast<const F *>(a.f_in);
     F *fo = static_cast<F *>(a.f_out);
