@@ -723,6 +723,7 @@ __device__ __forceinline__ bool needs_correction(const DevCell *cells, int64_t c
 // a.sel (REG: a list of cells without FINER or WALL faces).
 template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false, bool REG = false>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
+    static_assert(T % 64 == 0, "whole waves: the wave sums read every lane");
     __shared__ StepSmem<F, NH, T> sm;
     const uint32_t b = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const int64_t c = a.sel ? int64_t(as_const_space(a.sel)[b]) : int64_t(b);
