@@ -606,7 +606,7 @@ def main():
             "value": rk["cvu"], "unit": "CVU/s",
             "trial_evaluations_per_s": trials / k_s,
             "roofline": {"bound": "alu", "kernel": "k_korobov<double> (eqs. 4-6; the step's transport launch, "
-                         "under 1% of the time, inside the same events)", "achieved": flops / k_s / 1e12,
+                         "under 2% of the time, inside the same events)", "achieved": flops / k_s / 1e12,
                          "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s", "frac": flops / k_s / 1e12 / FP64_VECTOR_PEAK_TFS,
                          "algorithmic_flops_per_launch": flops, "kernel_ms_mean": k_s * 1e3},
             "status": int(rk["rc"])}
@@ -652,6 +652,15 @@ def main():
         "conservation_drift_rel": {"mass": float(r["drift"][0]), "energy": float(r["drift"][4])},
         "status": int(r["rc"]),
     }
+    if args.workload == "korobov16_v8":
+        # the collision dominates: FP64 arithmetic on data held on chip
+        flops, _ = korobov_flops(r)
+        k_s = float(np.mean(r["k_ms"])) / 1e3
+        out["roofline"] = {"bound": "alu", "kernel": "k_korobov<double> (eqs. 4-6; the step's transport launch, "
+                           "under 2% of the time, inside the same events)", "achieved": flops / k_s / 1e12,
+                           "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                           "frac": flops / k_s / 1e12 / FP64_VECTOR_PEAK_TFS, "traffic": None,
+                           "algorithmic_flops_per_launch": flops, "kernel_ms_mean": k_s * 1e3}
     if errors is not None:
         out["error_vs_oracle"] = errors
     if secondary:
