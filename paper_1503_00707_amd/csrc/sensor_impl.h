@@ -473,7 +473,8 @@ constexpr int kFluxRec = 71;
 struct HybArgs {
     const uint8_t *mask;  // effective mask (1 kinetic)
     uint8_t *prev;        // mask of the previous hybrid step
-    uint8_t *rows;        // 1: write Mt(U) into the state buffer before the step
+    uint8_t *rows;        // bit 0: write Mt(U) into the state buffer before the step;
+                          // bit 1: a kinetic cell with a fluid face neighbour
     double *flux;         // [n][kFluxRec] separable sums of fluid cells' Maxwellians
     double *face;         // [n][6][5] outgoing half-range fluxes of kinetic cells next to fluid ones
     int32_t closed;       // fluid-fluid faces: continuous half-range integrals (erf form)
@@ -535,20 +536,26 @@ __device__ inline bool maxwell_serial(const double U[5], const VelGrid &g, doubl
 
 // Per cell, one thread: fluid cells get the separable sums of their
 // Maxwellian; the cells whose state buffer row must hold Mt(U) this step
-// are flagged (fluid cells next to a kinetic one, cells turning kinetic);
-// the previous mask is updated.
+// are flagged (fluid cells next to a kinetic one, cells turning kinetic),
+// and so are the kinetic cells next to a fluid one (the step kernel reads
+// that one byte instead of its neighbours' masks); the previous mask is
+// updated.
 __global__ __launch_bounds__(256) void k_fluid_state(StepArgs a, HybArgs h) {
     const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x, n = a.n_cells;
     if (c >= n) return;
     const int m = h.mask[c], pm = h.prev[c];
     const DevCell &cell = a.cells[c];
-    bool kin_nb = false;
+    bool kin_nb = false, fluid_nb = false;
     for (int f = 0; f < 6; ++f) {
         const int ty = cell.type[f];
         const int k = ty == DVM_FACE_FINER ? 4 : (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) ? 1 : 0;
-        for (int q = 0; q < k; ++q) kin_nb |= h.mask[cell.nbr[f][q]] != 0;
+        for (int q = 0; q < k; ++q) {
+            const bool kin = h.mask[cell.nbr[f][q]] != 0;
+            kin_nb |= kin;
+            fluid_nb |= !kin;
+        }
     }
-    h.rows[c] = uint8_t((m == 0 && kin_nb) || (m == 1 && pm == 0));
+    h.rows[c] = uint8_t(((m == 0 && kin_nb) || (m == 1 && pm == 0)) | ((m == 1 && fluid_nb) ? 2 : 0));
     h.prev[c] = uint8_t(m);
     if (m) return;
     double U[5], u[3], sT, C, d[5];
@@ -602,7 +609,7 @@ __global__ __launch_bounds__(T) void k_hybrid_rows(StepArgs a, HybArgs h) {
     constexpr int64_t NV = 8 * NH * NH * NH;
     __shared__ MaxwellSmem<F, NH> sm;
     const int64_t c = blockIdx.x, n = a.n_cells;
-    if (!h.rows[c]) return;
+    if (!(h.rows[c] & 1)) return;
     const double rho = a.mom[c];
     const double u[3] = {a.mom[n + c] / rho, a.mom[2 * n + c] / rho, a.mom[3 * n + c] / rho};
     const double Tt = (2.0 * a.mom[4 * n + c] / rho - (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / 3.0;
@@ -723,14 +730,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     __shared__ StepSmem<F, NH, T> sm;
     const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     if (!h.mask[c]) return;
-    const CellView cell(a.cells, c);
-    bool fluid_nb = false;
-    for (int f = 0; f < 6; ++f) {
-        const int ty = cell.type_rt(f);
-        const int k = ty == DVM_FACE_FINER ? 4 : (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) ? 1 : 0;
-        for (int q = 0; q < k; ++q) fluid_nb |= h.mask[cell.nbr_rt(f, q)] == 0;
-    }
-    if (fluid_nb) {
+    // one byte, written by k_fluid_state: whether a face neighbour is fluid
+    if (h.rows[c] & 2) {
         const HybHook hook{h};
         step_cell<F, NH, T, FENCE, NT, false, false, HybHook>(a, c, sm, hook);
     } else if (needs_correction(a.cells, c)) {
