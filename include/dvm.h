@@ -75,8 +75,8 @@ extern "C" {
 #define DVM_PREC_FP64 0         /* f stored and transported in FP64 */
 #define DVM_PREC_FP32 1         /* f in FP32; moments, Maxwellian, correction in FP64 */
 #define DVM_SCHEME_UPWIND1 0
-#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction (fused engine;
-                                   the workspace then also holds 3 face-value planes) */
+#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction (the workspace
+                                   then also holds 3 face-value planes) */
 #define DVM_COLL_EXP 0          /* f' = Mt + (f* - Mt) exp(-dt/tau) */
 #define DVM_COLL_EULER 1        /* f' = f* + dt/tau (Mt - f*) */
 #define DVM_COLL_OFF 2          /* f' = f* */
@@ -135,8 +135,8 @@ typedef struct {
     size_t f_bytes;           /* one state buffer; two are bound (ping-pong) */
     size_t moments_bytes;     /* FP64 [5][n_cells] */
     size_t tables_bytes;      /* device mesh tables */
-    size_t ws_bytes;          /* ghost tables, flags, reduction partials, records of the
-                                 deferred-collision engine, MUSCL face values */
+    size_t ws_bytes;          /* ghost tables, flags, reduction partials, MUSCL face values,
+                                 hybrid masks and flux records, Korobov trial table */
     int64_t n_cells;
     int64_t nv_total;         /* N^3 */
 } dvm_sizes;
@@ -263,9 +263,8 @@ int dvm_check(dvm_solver *s, void *stream, dvm_diag *out);
 
 /*
  * Step-kernel shapes (autotuning).  A shape is (threads per workgroup, waves
- * per EU variant) of the selected engine's main kernel (see dvm_tune_engine);
- * each solver also chooses an XCD cell grouping (fused engine: runs of
- * consecutive Morton cells kept on one XCD's L2) and plain or non-temporal
+ * per EU variant) of the fused step kernel; each solver also chooses an XCD
+ * cell grouping (runs of consecutive Morton cells kept on one XCD's L2) and plain or non-temporal
  * stores of the new state.  dvm_tune_shapes lists the shapes compiled for the
  * solver's velocity grid (at most cap; *n the total).  dvm_tune_set returns
  * DVM_ERR_UNSUPPORTED for a shape that does not exist, DVM_ERR_ARG for
@@ -277,25 +276,7 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
 int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store);
 
 /*
- * dvm_tune_engine -- choose how a step is executed (both compute the same
- * Lie-split step: transport, eq. 2, then BGK relaxation to the eq. 6
- * corrected Maxwellian):
- *   0  fused (default): one workgroup per cell runs transport, moments,
- *      Maxwellian and relaxation; the state buffer holds f;
- *   1  deferred collision: one workgroup per (cell, velocity
- *      octant) runs the transport of the relaxed state and stores f*; a small
- *      per-cell pass then builds the relaxation record (corrected Maxwellian
- *      tables, relaxation factor, wall densities) that the next transport
- *      applies when it reads f*.  dvm_moments / dvm_f_to_canonical present f.
- * engine < 0 only queries; *previous (may be NULL) receives the engine in use.
- * Engine 1 is first order only (DVM_ERR_UNSUPPORTED with DVM_SCHEME_MUSCL).
- * The shapes listed by dvm_tune_shapes and set by dvm_tune_set are those of
- * the selected engine.
- */
-int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
-
-/*
- * dvm_tune_split -- fused engine, first order: step the cells that have no
+ * dvm_tune_split -- first order: step the cells that have no
  * FINER or WALL face (a level jump seen from the coarse side, or a wall) in a
  * reduced kernel and the others in a second launch of the full kernel
  * (enable = 1), or every cell in one launch (enable = 0, the default; each
@@ -311,7 +292,7 @@ int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous);
 int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t wpe_irr, int32_t *previous);
 
 /*
- * dvm_tune -- project autotuner for one solver (fused engine): time every
+ * dvm_tune -- project autotuner for one solver: time every
  * compiled step shape x XCD cell grouping {1, 8, 64, 512} x store kind (plain
  * or non-temporal) with reps trial steps on the solver's own state, keep the
  * fastest (dvm_tune_get reports it).  cache_path (may be NULL) names a text
@@ -321,8 +302,8 @@ int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t w
  * is rewritten through a temporary and renamed).  The trial steps read the
  * current state and write the other state buffer and the moments buffer; the
  * moments are then recomputed from the current state (within rounding of the
- * step's own values).  Synchronises.  DVM_ERR_UNSUPPORTED for the deferred
- * engine or while fluid cells of a hybrid step hold no f; DVM_ERR_ARG if the
+ * step's own values).  Synchronises.  DVM_ERR_UNSUPPORTED while fluid cells
+ * of a hybrid step hold no f; DVM_ERR_ARG if the
  * cache cannot be written.
  */
 int dvm_tune(dvm_solver *s, const char *cache_path, int32_t reps, int32_t *from_cache, void *stream);
@@ -368,7 +349,7 @@ int dvm_load(dvm_solver *s, dvm_mlp *net, const char *path, void *stream);
  * Batched steps (many independent flow instances in one graph launch).
  *
  * dvm_batch_create -- group n bound solvers (same storage precision, first
- * order, fused engine) by velocity grid; inside a group the instances are
+ * order) by velocity grid; inside a group the instances are
  * ordered by decreasing cost (cells x velocities) so that the largest start
  * first.  Each instance steps with its own dt = cfl h_min / max sum |xi|.
  * The solvers must outlive the batch; the batch owns host objects and the
@@ -461,8 +442,8 @@ void dvm_destroy_batch(dvm_batch *b);
  * so fluid cells still conserve among themselves); faces next to a kinetic
  * cell keep the discrete sums, which that cell's transport sees.  A cell that becomes kinetic starts from
  * Mt(U); one that becomes fluid keeps the moments of its f.  Cells touching
- * a non-periodic domain face stay kinetic.  Needs params.hybrid = 1, the
- * fused engine and first order (DVM_ERR_UNSUPPORTED otherwise).  With every
+ * a non-periodic domain face stay kinetic.  Needs params.hybrid = 1 and
+ * first order (DVM_ERR_UNSUPPORTED otherwise).  With every
  * cell kinetic it is dvm_step.  After hybrid steps the moments buffer is the
  * state of fluid cells (whose f rows are stale): dvm_moments then recomputes
  * kinetic cells from f and copies fluid cells' conserved moments, and must be

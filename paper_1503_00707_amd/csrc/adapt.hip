@@ -604,8 +604,6 @@ int dvm_adapt_remap(const dvm_solver *from, dvm_solver *to, void *ws, size_t ws_
     const Leaves A{la, ia, ka, na}, B{lb, ib, kb, nb};
     hipLaunchKernelGGL(k_keys, dim3(unsigned(blocks(na))), dim3(256), 0, st, A, g, ka);
     hipLaunchKernelGGL(k_keys, dim3(unsigned(blocks(nb))), dim3(256), 0, st, B, g, kb);
-    e = solver_make_plain(const_cast<dvm_solver *>(from), st);
-    if (e != hipSuccess) return hip_fail(e, "state conversion");
     // the internal velocity order is the same on both sides: remap rows as they are
     if (from->fp64)
         hipLaunchKernelGGL(k_remap<double>, dim3(unsigned(nb)), dim3(256), 0, st, A, B, g,

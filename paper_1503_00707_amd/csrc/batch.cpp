@@ -267,10 +267,6 @@ int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream) {
         if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "every solver must be bound and uploaded");
         if (s->hybrid_fluid)
             return fail(DVM_ERR_UNSUPPORTED, "a solver holds fluid cells from hybrid steps (their f is stale)");
-        if (s->relax_pending) {
-            hipError_t e = solver_make_plain(s, st);
-            if (e != hipSuccess) return hip_fail(e, "state conversion");
-        }
     }
     if (!b->args_valid || !in_step(b)) {
         // the graphs read the argument block by address: no re-capture needed
@@ -288,7 +284,6 @@ int dvm_batch_step(dvm_batch *b, int32_t n_steps, void *stream) {
         for (auto *s : b->s) {
             s->cur ^= 1;
             s->steps++;
-            s->lazy_valid = false;
         }
     }
     return DVM_OK;
@@ -304,10 +299,6 @@ int dvm_batch_tune(dvm_batch *b, int32_t reps, const char *cache_path, void *str
         if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "every solver must be bound and uploaded");
         if (s->hybrid_fluid)
             return fail(DVM_ERR_UNSUPPORTED, "a solver holds fluid cells from hybrid steps (their f is stale)");
-        if (s->relax_pending) {
-            hipError_t e = solver_make_plain(s, st);
-            if (e != hipSuccess) return hip_fail(e, "state conversion");
-        }
     }
     if (!b->args_valid || !in_step(b)) {
         int rc = write_args(b, st);

@@ -170,47 +170,6 @@ hipError_t launch_lbm_moments(int q, bool fp64, const void *f, const LbmCell *ce
 hipError_t launch_lbm_init(int q, bool fp64, const double *prim, void *f, int64_t n, int *flag, hipStream_t st);
 hipError_t launch_lbm_canon(int q, bool fp64, const void *src, void *dst, int64_t n, bool to_canon, hipStream_t st);
 
-// Deferred-collision engine (lazy_impl.h).
-struct UnitArgsPub {
-    const void *f_in;
-    void *f_out;
-    const void *tab;
-    double *partials;
-    const DevCell *cells;
-    const void *ghost_in;
-    const void *wall_m1;
-    const void *null_rec;    // the identity record; the sweep requires null_rec == tab + n_cells * stride
-    int64_t n_cells;
-    double dt;
-    double h0;
-    VelGrid g;
-};
-struct TableArgsPub {
-    const double *partials;
-    void *tab;
-    double *mom;
-    const DevCell *cells;
-    const double *wall_den;
-    int *flag;
-    int64_t n_cells;
-    double dt;
-    VelGrid g;
-    int collide;
-    int collision;
-    int tau_mode;
-    double tau_or_kn;
-};
-hipError_t launch_unit_moments(bool fp64, const UnitArgsPub &a, hipStream_t st);
-hipError_t launch_sweep(bool fp64, const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st);
-hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st);
-hipError_t launch_identity(bool fp64, void *tab, int64_t n, int nh, hipStream_t st);
-hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, void *dst, int64_t n, int nh,
-                                hipStream_t st);
-hipError_t launch_materialize(bool fp64, void *fstar, void *tab, int64_t n, int nh, hipStream_t st);
-hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, double w, hipStream_t st);
-int table_stride(int nh);
-bool have_sweep_kernel(int nh, int threads, int wg_per_cu);
-int list_sweep_kernels(int nh, int *threads, int *wg_per_cu, int cap);
 
 // per-precision instantiations (kernels_f32.hip, kernels_f64.hip)
 #define DVM_DECLARE_PREC(SUF)                                                                            \
@@ -220,14 +179,7 @@ int list_sweep_kernels(int nh, int *threads, int *wg_per_cu, int cap);
     hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
     hipError_t launch_face_##SUF(const StepArgs &a, hipStream_t st);                                     \
     hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
-    hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);              \
-    hipError_t launch_unit_moments_##SUF(const UnitArgsPub &a, hipStream_t st);                          \
-    hipError_t launch_sweep_##SUF(const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st); \
-    hipError_t launch_tables_##SUF(const TableArgsPub &a, hipStream_t st);                               \
-    hipError_t launch_identity_##SUF(void *tab, int64_t n, int nh, hipStream_t st);                      \
-    hipError_t launch_canon_relaxed_##SUF(const void *fstar, const void *tab, void *dst, int64_t n, int nh, \
-                                          hipStream_t st);                                               \
-    hipError_t launch_materialize_##SUF(void *fstar, void *tab, int64_t n, int nh, hipStream_t st);
+    hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);
 DVM_DECLARE_PREC(f32)
 DVM_DECLARE_PREC(f64)
 #undef DVM_DECLARE_PREC

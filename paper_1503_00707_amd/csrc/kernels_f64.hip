@@ -1,5 +1,5 @@
 // kernels_f64.hip -- step, init, moment and wall kernels for double storage.
-#include "sweep_impl.h"
+#include "step_impl.h"
 
 namespace dvm {
 
@@ -17,34 +17,6 @@ hipError_t launch_moments_f64(const void *f, double *out, int64_t n, const VelGr
 }
 hipError_t launch_wall_den_f64(const void *m1, double *den, const VelGrid &g, hipStream_t st) {
     return impl::wall_den_dispatch<double>(m1, den, g, st);
-}
-
-static_assert(sizeof(UnitArgsPub) == sizeof(impl::UnitArgs), "argument layout");
-static_assert(sizeof(TableArgsPub) == sizeof(impl::TableArgs), "argument layout");
-
-hipError_t launch_unit_moments_f64(const UnitArgsPub &a, hipStream_t st) {
-    impl::UnitArgs u;
-    __builtin_memcpy(&u, &a, sizeof u);
-    return impl::unit_dispatch<double>(u, st);
-}
-hipError_t launch_sweep_f64(const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st) {
-    impl::UnitArgs u;
-    __builtin_memcpy(&u, &a, sizeof u);
-    return impl::sweep_dispatch<double>(u, wg_per_cu, n_cu, nt, st);
-}
-hipError_t launch_tables_f64(const TableArgsPub &a, hipStream_t st) {
-    impl::TableArgs t;
-    __builtin_memcpy(&t, &a, sizeof t);
-    return impl::tables_dispatch<double>(t, st);
-}
-hipError_t launch_identity_f64(void *tab, int64_t n, int nh, hipStream_t st) {
-    return impl::identity_dispatch<double>(tab, n, nh, st);
-}
-hipError_t launch_canon_relaxed_f64(const void *fstar, const void *tab, void *dst, int64_t n, int nh, hipStream_t st) {
-    return impl::canon_relaxed_dispatch<double>(fstar, tab, dst, n, nh, st);
-}
-hipError_t launch_materialize_f64(void *fstar, void *tab, int64_t n, int nh, hipStream_t st) {
-    return impl::materialize_dispatch<double>(fstar, tab, n, nh, st);
 }
 
 }  // namespace dvm

@@ -2,7 +2,7 @@
 // precision dispatch of the launch interface.
 #include <hip/hip_runtime.h>
 
-#include "sweep_impl.h"
+#include "step_impl.h"
 
 namespace dvm {
 namespace {
@@ -134,32 +134,6 @@ hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid
     return fp64 ? launch_wall_den_f64(m1, den, g, st) : launch_wall_den_f32(m1, den, g, st);
 }
 
-hipError_t launch_unit_moments(bool fp64, const UnitArgsPub &a, hipStream_t st) {
-    return fp64 ? launch_unit_moments_f64(a, st) : launch_unit_moments_f32(a, st);
-}
-hipError_t launch_sweep(bool fp64, const UnitArgsPub &a, int wg_per_cu, int n_cu, bool nt, hipStream_t st) {
-    return fp64 ? launch_sweep_f64(a, wg_per_cu, n_cu, nt, st) : launch_sweep_f32(a, wg_per_cu, n_cu, nt, st);
-}
-hipError_t launch_tables(bool fp64, const TableArgsPub &a, hipStream_t st) {
-    return fp64 ? launch_tables_f64(a, st) : launch_tables_f32(a, st);
-}
-hipError_t launch_identity(bool fp64, void *tab, int64_t n, int nh, hipStream_t st) {
-    return fp64 ? launch_identity_f64(tab, n, nh, st) : launch_identity_f32(tab, n, nh, st);
-}
-hipError_t launch_canon_relaxed(bool fp64, const void *fstar, const void *tab, void *dst, int64_t n, int nh,
-                                hipStream_t st) {
-    return fp64 ? launch_canon_relaxed_f64(fstar, tab, dst, n, nh, st) : launch_canon_relaxed_f32(fstar, tab, dst, n, nh, st);
-}
-hipError_t launch_materialize(bool fp64, void *fstar, void *tab, int64_t n, int nh, hipStream_t st) {
-    return fp64 ? launch_materialize_f64(fstar, tab, n, nh, st) : launch_materialize_f32(fstar, tab, n, nh, st);
-}
-hipError_t launch_sum_partials(const double *partials, double *out, int64_t n, double w, hipStream_t st) {
-    hipLaunchKernelGGL(impl::k_sum_partials<0>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, partials, out, n, w);
-    return hipGetLastError();
-}
-int table_stride(int nh) { return impl::tab_stride(nh); }
-bool have_sweep_kernel(int nh, int threads, int k) { return impl::sweep_config_exists(nh, threads, k); }
-int list_sweep_kernels(int nh, int *threads, int *k, int cap) { return impl::sweep_config_list(nh, threads, k, cap); }
 
 hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
                               int n_part, double *out, hipStream_t st) {

@@ -229,7 +229,6 @@ int dvm_tune(dvm_solver *s, const char *cache_path, int32_t reps, int32_t *from_
     if (!s) return fail(DVM_ERR_ARG, "null solver");
     if (from_cache) *from_cache = 0;
     if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
-    if (s->engine != 0) return fail(DVM_ERR_UNSUPPORTED, "dvm_tune chooses the fused engine's shapes");
     if (s->hybrid_fluid) return fail(DVM_ERR_UNSUPPORTED, "fluid cells hold no f: tune before hybrid steps");
     if (reps < 1) return fail(DVM_ERR_ARG, "reps must be >= 1");
     const TuneKey key{"step", s->nh, s->fp64 ? 1 : 0, s->muscl ? 1 : 0};
@@ -244,8 +243,7 @@ int dvm_tune(dvm_solver *s, const char *cache_path, int32_t reps, int32_t *from_
         return DVM_OK;
     }
     hipStream_t st = S(stream);
-    hipError_t e = solver_make_plain(s, st);
-    if (e != hipSuccess) return hip_fail(e, "state conversion");
+    hipError_t e = hipSuccess;
     double dt = 0.0;
     int rc = dvm_dt(s, 0.5, &dt);
     if (rc) return rc;

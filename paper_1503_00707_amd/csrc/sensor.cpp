@@ -64,8 +64,7 @@ int dvm_labels(dvm_solver *s, float *r, void *stream) {
     clear_error();
     if (!s || !r) return fail(DVM_ERR_ARG, "null argument");
     if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
-    hipError_t e = solver_make_plain(s, S(stream));
-    if (e == hipSuccess) e = launch_labels(s->fp64, s->f[s->cur], r, s->n, s->g, S(stream));
+    const hipError_t e = launch_labels(s->fp64, s->f[s->cur], r, s->n, s->g, S(stream));
     return e == hipSuccess ? DVM_OK : hip_fail(e, "labels");
 }
 
@@ -180,15 +179,14 @@ int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double 
     if (!s || !mask) return fail(DVM_ERR_ARG, "null argument");
     if (!s->uploaded) return fail(DVM_ERR_WORKSPACE, "call dvm_upload first");
     if (!s->hybrid) return fail(DVM_ERR_UNSUPPORTED, "create the solver with params.hybrid = 1");
-    if (s->muscl || s->engine != 0) return fail(DVM_ERR_UNSUPPORTED, "the hybrid step is first order, fused engine");
+    if (s->muscl) return fail(DVM_ERR_UNSUPPORTED, "the hybrid step is first order");
     if (n_steps < 0) return fail(DVM_ERR_ARG, "n_steps < 0");
     if (!(dt > 0)) {
         int rc = dvm_dt(s, cfl, &dt);
         if (rc) return rc;
     }
     hipStream_t st = S(stream);
-    hipError_t e = solver_make_plain(s, st);
-    if (e == hipSuccess) e = launch_mask_eff(mask, hyb_mask(s), s->tables, s->n, st);
+    hipError_t e = launch_mask_eff(mask, hyb_mask(s), s->tables, s->n, st);
     if (e != hipSuccess) return hip_fail(e, "hybrid mask");
     const HybArgsPub h{hyb_mask(s), hyb_prev(s), hyb_rows(s), hyb_flux(s), hyb_face(s),
                        s->p.fluid_flux == DVM_FLUX_CLOSED ? 1 : 0, 0};
@@ -200,7 +198,6 @@ int dvm_hybrid_step(dvm_solver *s, const uint8_t *mask, int32_t n_steps, double 
         if (e != hipSuccess) return hip_fail(e, "hybrid step");
         s->cur ^= 1;
         s->steps++;
-        s->lazy_valid = false;
         s->hybrid_fluid = true;  // conservative: the mask lives on the device
         if (s->p.check_every > 0 && s->steps % s->p.check_every == 0) {
             e = launch_global_sums(s->mom, s->tables, s->n, s->m->h0, s->partials(), kPartials, s->sums(), st);

@@ -11,63 +11,9 @@
 
 using namespace dvm;
 
-static UnitArgsPub unit_args(const dvm_solver *s, const void *fin, void *fout, double dt) {
-    UnitArgsPub u{};
-    u.f_in = fin;
-    u.f_out = fout;
-    u.tab = s->tab();
-    u.partials = s->lpart();
-    u.cells = s->tables;
-    u.ghost_in = s->gin();
-    u.wall_m1 = s->m1();
-    u.null_rec = s->null_rec();
-    u.n_cells = s->n;
-    u.dt = dt;
-    u.h0 = s->m->h0;
-    u.g = s->g;
-    return u;
-}
-
-static TableArgsPub table_args(const dvm_solver *s, int collide, double dt, double *mom) {
-    TableArgsPub t{};
-    t.partials = s->lpart();
-    t.tab = s->tab();
-    t.mom = mom;
-    t.cells = s->tables;
-    t.wall_den = s->den();
-    t.flag = s->flag();
-    t.n_cells = s->n;
-    t.dt = dt;
-    t.g = s->g;
-    t.collide = collide;
-    t.collision = s->p.collision;
-    t.tau_mode = s->p.tau_mode;
-    t.tau_or_kn = s->p.tau_or_kn;
-    return t;
-}
-
-// Make the records describe the current buffer as f* with no pending
-// relaxation: identity records, then the partial moments and the wall
-// densities of the current state.
-static hipError_t ensure_lazy(dvm_solver *s, hipStream_t st) {
-    if (s->lazy_valid) return hipSuccess;
-    hipError_t e = launch_identity(s->fp64, s->tab(), s->n, s->nh, st);
-    if (e != hipSuccess) return e;
-    UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
-    e = launch_unit_moments(s->fp64, u, st);
-    if (e != hipSuccess) return e;
-    TableArgsPub t = table_args(s, 0, 0.0, s->mom);
-    e = launch_tables(s->fp64, t, st);
-    if (e != hipSuccess) return e;
-    s->lazy_valid = true;
-    s->relax_pending = false;
-    return hipSuccess;
-}
-
-// Apply a pending relaxation in place so that the buffer holds f itself.
 namespace {
 // two launches (reduced kernel over the regular cells, full kernel over the
-// rest) instead of one: fused engine, first order, kernels compiled
+// rest) instead of one: first order, kernels compiled
 bool use_split(const dvm_solver *s) {
     return s->split && !s->muscl && s->n_reg > 0 && have_regular_kernel(s->nh, s->cfg.threads, s->cfg.wpe) &&
            have_kernel(s->nh, s->cfg_irr.threads, s->cfg_irr.wpe);
@@ -96,19 +42,8 @@ StepArgs dvm::solver_step_args(const dvm_solver *s, double dt) {
     return a;
 }
 
-hipError_t dvm::solver_make_plain(dvm_solver *s, hipStream_t st) {
-    if (!s->relax_pending) return hipSuccess;
-    hipError_t e = launch_materialize(s->fp64, s->f[s->cur], s->tab(), s->n, s->nh, st);
-    if (e != hipSuccess) return e;
-    s->relax_pending = false;
-    return hipSuccess;
-}
-
 hipError_t dvm::solver_state_replaced(dvm_solver *s, hipStream_t st) {
-    s->lazy_valid = false;
-    s->relax_pending = false;
-    hipError_t e = ensure_lazy(s, st);
-    if (e == hipSuccess) e = solver_reset_hybrid(s, st);
+    hipError_t e = solver_reset_hybrid(s, st);
     if (e == hipSuccess) e = launch_moments(s->fp64, s->f[s->cur], s->mom, s->n, s->g, st);
     s->hybrid_fluid = false;
     return e;
@@ -210,10 +145,6 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->off_flag = o; o += 256;
     s->off_part = o; o += align256(size_t(kPartials) * 5 * 8);
     s->off_sums = o; o += 256;
-    // n records and the identity record after them (one table for the sweep)
-    s->off_tab = o;  o += align256(size_t(s->n + 1) * size_t(table_stride(nh)) * fs);
-    s->off_null = s->off_tab + size_t(s->n) * size_t(table_stride(nh)) * fs;
-    s->off_lpart = o; o += align256(size_t(8) * size_t(s->n) * 5 * 8);
     s->muscl = p->scheme == DVM_SCHEME_MUSCL;
     s->off_face = o;
     if (s->muscl) o += 3 * s->f_bytes;
@@ -244,7 +175,6 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
         }
     s->cfg_irr = s->cfg;
     s->ws_bytes = o;
-    if (nh == 12) s->sweep_k = 3;
     *out = s;
     return DVM_OK;
 }
@@ -321,8 +251,6 @@ int dvm_upload(dvm_solver *s, void *stream) {
         e = launch_wall_den(s->fp64, s->m1(), s->den(), s->g, st);
         if (e != hipSuccess) return hip_fail(e, "wall denominators");
     }
-    e = launch_identity(s->fp64, s->null_rec(), 1, s->nh, st);
-    if (e != hipSuccess) return hip_fail(e, "identity record");
     if (s->korobov()) {
         e = hipMemcpyAsync(s->ws + s->off_kor, s->kor_host.data(), s->kor_host.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice, st);
@@ -360,10 +288,6 @@ int dvm_init_maxwellian(dvm_solver *s, const double *prim, void *stream) {
     a.f_out = s->f[0];
     hipError_t e = launch_init(s->fp64, a, S(stream));
     if (e != hipSuccess) return hip_fail(e, "init");
-    s->lazy_valid = false;
-    s->relax_pending = false;
-    e = ensure_lazy(s, S(stream));
-    if (e != hipSuccess) return hip_fail(e, "init records");
     e = solver_reset_hybrid(s, S(stream));
     if (e != hipSuccess) return hip_fail(e, "hybrid masks");
     s->hybrid_fluid = false;
@@ -393,60 +317,48 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     }
     StepArgs a = solver_step_args(s, dt);
     hipStream_t st = S(stream);
-    hipError_t e = s->engine == 1 ? ensure_lazy(s, st) : solver_make_plain(s, st);
-    if (e != hipSuccess) return hip_fail(e, "state conversion");
+    hipError_t e = hipSuccess;
     for (int it = 0; it < n_steps; ++it) {
-        if (s->engine == 1) {
-            UnitArgsPub u = unit_args(s, s->f[s->cur], s->f[s->cur ^ 1], dt);
-            e = launch_sweep(s->fp64, u, s->sweep_k, s->n_cu, s->unit_nt != 0, st);
-            if (e != hipSuccess) return hip_fail(e, "transport sweep");
-            TableArgsPub t = table_args(s, 1, dt, s->mom);
-            e = launch_tables(s->fp64, t, st);
-            if (e != hipSuccess) return hip_fail(e, "collision records");
-            s->relax_pending = s->p.collision != DVM_COLL_OFF;
+        a.f_in = s->f[s->cur];
+        a.f_out = s->f[s->cur ^ 1];
+        if (s->muscl) {
+            e = launch_face(s->fp64, a, st);
+            if (e != hipSuccess) return hip_fail(e, "MUSCL face values");
+        }
+        if (use_split(s)) {
+            StepArgs ar = a;
+            ar.sel = s->sel();
+            ar.n_sel = s->n_reg;
+            StepConfig cr = s->cfg;
+            cr.regular = 1;
+            e = s->n_reg > 0 ? launch_step(s->fp64, ar, cr, st) : hipSuccess;
+            if (e == hipSuccess && s->n > s->n_reg) {
+                StepArgs ai = a;
+                ai.sel = s->sel() + s->n_reg;
+                ai.n_sel = s->n - s->n_reg;
+                StepConfig ci = s->cfg;  // stores and grouping as chosen; its own shape
+                ci.threads = s->cfg_irr.threads;
+                ci.wpe = s->cfg_irr.wpe;
+                ci.regular = 0;
+                e = launch_step(s->fp64, ai, ci, st);
+            }
         } else {
-            a.f_in = s->f[s->cur];
-            a.f_out = s->f[s->cur ^ 1];
-            if (s->muscl) {
-                e = launch_face(s->fp64, a, st);
-                if (e != hipSuccess) return hip_fail(e, "MUSCL face values");
-            }
-            if (use_split(s)) {
-                StepArgs ar = a;
-                ar.sel = s->sel();
-                ar.n_sel = s->n_reg;
-                StepConfig cr = s->cfg;
-                cr.regular = 1;
-                e = s->n_reg > 0 ? launch_step(s->fp64, ar, cr, st) : hipSuccess;
-                if (e == hipSuccess && s->n > s->n_reg) {
-                    StepArgs ai = a;
-                    ai.sel = s->sel() + s->n_reg;
-                    ai.n_sel = s->n - s->n_reg;
-                    StepConfig ci = s->cfg;  // stores and grouping as chosen; its own shape
-                    ci.threads = s->cfg_irr.threads;
-                    ci.wpe = s->cfg_irr.wpe;
-                    ci.regular = 0;
-                    e = launch_step(s->fp64, ai, ci, st);
-                }
-            } else {
-                e = launch_step(s->fp64, a, s->cfg, st);
-            }
-            if (e != hipSuccess) return hip_fail(e, "step");
-            if (s->korobov()) {
-                KorArgs k{};
-                k.f = a.f_out;
-                k.table = s->kor();
-                k.n_cells = s->n;
-                k.p = int(s->kor_p);
-                k.w0 = 8.0 * s->p.vmax[0] * s->p.vmax[0] * s->p.vmax[0] / double(s->kor_p);
-                k.dt_kn = dt / s->p.tau_or_kn;
-                k.vmax = s->p.vmax[0];
-                k.g = s->g;
-                k.flag = s->flag();
-                e = launch_korobov(s->fp64, k, st);
-                if (e != hipSuccess) return hip_fail(e, "Korobov collision");
-            }
-            s->lazy_valid = false;
+            e = launch_step(s->fp64, a, s->cfg, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "step");
+        if (s->korobov()) {
+            KorArgs k{};
+            k.f = a.f_out;
+            k.table = s->kor();
+            k.n_cells = s->n;
+            k.p = int(s->kor_p);
+            k.w0 = 8.0 * s->p.vmax[0] * s->p.vmax[0] * s->p.vmax[0] / double(s->kor_p);
+            k.dt_kn = dt / s->p.tau_or_kn;
+            k.vmax = s->p.vmax[0];
+            k.g = s->g;
+            k.flag = s->flag();
+            e = launch_korobov(s->fp64, k, st);
+            if (e != hipSuccess) return hip_fail(e, "Korobov collision");
         }
         s->cur ^= 1;
         s->steps++;
@@ -481,14 +393,7 @@ int dvm_moments(dvm_solver *s, double *out, void *stream) {
     if (s->hybrid_fluid && out == s->mom)
         return fail(DVM_ERR_ARG, "after hybrid steps the moments buffer holds the fluid cells' state: pass "
                                  "another output buffer");
-    hipError_t e;
-    if (s->relax_pending) {
-        UnitArgsPub u = unit_args(s, s->f[s->cur], nullptr, 0.0);
-        e = launch_unit_moments(s->fp64, u, S(stream));
-        if (e == hipSuccess) e = launch_sum_partials(s->lpart(), out, s->n, s->g.w, S(stream));
-    } else {
-        e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
-    }
+    hipError_t e = launch_moments(s->fp64, s->f[s->cur], out, s->n, s->g, S(stream));
     // fluid cells of a hybrid step carry only their conserved moments
     if (e == hipSuccess) e = solver_fluid_moments(s, out, S(stream));
     if (e != hipSuccess) return hip_fail(e, "moments");
@@ -517,11 +422,7 @@ int dvm_check(dvm_solver *s, void *stream, dvm_diag *out) {
 int dvm_f_to_canonical(const dvm_solver *s, const void *f_internal, void *f_canon, void *stream) {
     clear_error();
     if (!s || !f_internal || !f_canon) return fail(DVM_ERR_ARG, "null argument");
-    hipError_t e;
-    if (s->relax_pending && f_internal == s->f[s->cur])
-        e = launch_canon_relaxed(s->fp64, f_internal, s->tab(), f_canon, s->n, s->nh, S(stream));
-    else
-        e = launch_to_canonical(s->fp64, true, f_internal, f_canon, s->n, s->nh, S(stream));
+    hipError_t e = launch_to_canonical(s->fp64, true, f_internal, f_canon, s->n, s->nh, S(stream));
     if (e != hipSuccess) return hip_fail(e, "to_canonical");
     return DVM_OK;
 }
@@ -532,11 +433,9 @@ int dvm_f_from_canonical(dvm_solver *s, const void *f_canon, void *f_internal, v
     hipError_t e = launch_to_canonical(s->fp64, false, f_canon, f_internal, s->n, s->nh, S(stream));
     if (e != hipSuccess) return hip_fail(e, "from_canonical");
     if (f_internal == s->f[s->cur] && s->uploaded) {
-        // the buffer now holds f itself: fresh records, moments and wall densities
-        s->lazy_valid = false;
-        s->relax_pending = false;
-        e = ensure_lazy(s, S(stream));
-        if (e != hipSuccess) return hip_fail(e, "records");
+        // the buffer holds a new state: its moments, fresh hybrid masks
+        e = launch_moments(s->fp64, f_internal, s->mom, s->n, s->g, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "moments");
         e = solver_reset_hybrid(s, S(stream));
         if (e != hipSuccess) return hip_fail(e, "hybrid masks");
         s->hybrid_fluid = false;
@@ -548,7 +447,7 @@ int dvm_tune_shapes(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t
     clear_error();
     if (!s || !n || (cap > 0 && (!threads || !wpe))) return fail(DVM_ERR_ARG, "null argument");
     int t[64], w[64];
-    const int total = s->engine == 1 ? list_sweep_kernels(s->nh, t, w, 64) : list_kernels(s->nh, t, w, 64);
+    const int total = list_kernels(s->nh, t, w, 64);
     for (int k = 0; k < total && k < cap && k < 64; ++k) {
         threads[k] = t[k];
         wpe[k] = w[k];
@@ -562,15 +461,6 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
     if (!s) return fail(DVM_ERR_ARG, "null solver");
     if (xcd_group < 1 || xcd_group > 4096 || (xcd_group & (xcd_group - 1)))
         return fail(DVM_ERR_ARG, "xcd_group must be a power of two in [1, 4096]");
-    if (s->engine == 1) {
-        if (!have_sweep_kernel(s->nh, threads, wpe))
-            return fail(DVM_ERR_UNSUPPORTED, "no sweep kernel with %d threads, %d workgroups per CU for N = %d",
-                        threads, wpe, 2 * s->nh);
-        s->sweep_k = wpe;
-        s->unit_nt = nt_store != 0;
-        s->cfg.xcd_group = xcd_group;
-        return DVM_OK;
-    }
     if (!have_kernel(s->nh, threads, wpe))
         return fail(DVM_ERR_UNSUPPORTED, "no step kernel with %d threads, wpe %d for N = %d", threads, wpe, 2 * s->nh);
     s->cfg.threads = threads;
@@ -583,14 +473,10 @@ int dvm_tune_set(dvm_solver *s, int32_t threads, int32_t wpe, int32_t xcd_group,
 int dvm_tune_get(const dvm_solver *s, int32_t *threads, int32_t *wpe, int32_t *xcd_group, int32_t *nt_store) {
     clear_error();
     if (!s || !threads || !wpe || !xcd_group || !nt_store) return fail(DVM_ERR_ARG, "null argument");
-    int t1[64], k1[64];
-    const int nk = list_sweep_kernels(s->nh, t1, k1, 64);
-    int k = s->sweep_k;
-    if (k == 0 && nk > 0) k = k1[0];
-    *threads = s->engine == 1 ? (nk > 0 ? t1[0] : 0) : s->cfg.threads;
-    *wpe = s->engine == 1 ? k : s->cfg.wpe;
+    *threads = s->cfg.threads;
+    *wpe = s->cfg.wpe;
     *xcd_group = s->cfg.xcd_group;
-    *nt_store = s->engine == 1 ? s->unit_nt : s->cfg.nt_store;
+    *nt_store = s->cfg.nt_store;
     return DVM_OK;
 }
 
@@ -607,20 +493,6 @@ int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t w
         s->cfg_irr.wpe = wpe_irr;
     }
     s->split = enable != 0;
-    return DVM_OK;
-}
-
-int dvm_tune_engine(dvm_solver *s, int32_t engine, int32_t *previous) {
-    clear_error();
-    if (!s) return fail(DVM_ERR_ARG, "null solver");
-    if (previous) *previous = s->engine;
-    if (engine < 0) return DVM_OK;  // query only
-    if (engine != 0 && engine != 1) return fail(DVM_ERR_ARG, "engine must be 0 (fused) or 1 (deferred collision)");
-    if (engine == 1 && s->muscl) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine is first order only");
-    if (engine == 1 && s->korobov()) return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine relaxes with BGK");
-    if (engine == 1 && size_t(s->n + 1) * size_t(table_stride(s->nh)) * (s->fp64 ? 8 : 4) >= (size_t(1) << 32))
-        return fail(DVM_ERR_UNSUPPORTED, "the deferred-collision engine addresses its records with 32-bit offsets");
-    s->engine = engine;
     return DVM_OK;
 }
 

@@ -54,14 +54,8 @@ struct dvm_solver {
     bool tables_pending = false;  // uploaded except the face tables of a device-table mesh
     int64_t steps = 0;
     bool has_inflow = false, has_wall = false;
-    // deferred-collision engine
-    int engine = 0;              // 0: fused (stores f), 1: deferred collision (stores f* + records)
-    int sweep_k = 0, unit_nt = 1;  // sweep workgroups per CU (0: first compiled), NT stores
     int n_cu = 0;                  // compute units of the bound device
-    size_t off_tab = 0, off_lpart = 0, off_null = 0;
-    bool lazy_valid = false;     // records describe f[cur] read as f*
-    bool relax_pending = false;  // some record is not the identity
-    // fused engine, first order: optionally step the cells without FINER or
+    // first order: optionally step the cells without FINER or
     // WALL faces ("regular") in a reduced kernel and the others in a second
     // launch (off by default: one launch takes the reduced code path per cell
     // and keeps Morton locality between the two kinds)
@@ -71,9 +65,6 @@ struct dvm_solver {
     std::vector<uint32_t> sel_host;
     dvm::StepConfig cfg_irr{};     // shape of the launch over the other cells
 
-    void *tab() const { return ws + off_tab; }
-    void *null_rec() const { return ws + off_null; }  // record n of the table section
-    double *lpart() const { return reinterpret_cast<double *>(ws + off_lpart); }
     void *gin() const { return ws + off_gin; }
     void *face() const { return muscl ? ws + off_face : nullptr; }
     void *m1() const { return ws + off_m1; }
@@ -104,8 +95,6 @@ struct dvm_mlp {
 };
 
 namespace dvm {
-// The state buffer holds f itself (applies a pending deferred relaxation).
-hipError_t solver_make_plain(dvm_solver *s, hipStream_t st);
 // Kernel arguments of one fused step of size dt (f_in / f_out left NULL).
 StepArgs solver_step_args(const dvm_solver *s, double dt);
 double solver_max_speed_sum(const dvm_solver *s);

@@ -27,7 +27,7 @@ EXPORTED = [
     "dvm_last_error", "dvm_balance", "dvm_create_mesh", "dvm_mesh_info", "dvm_mesh_export", "dvm_destroy_mesh",
     "dvm_create_solver", "dvm_buffer_sizes", "dvm_bind", "dvm_upload", "dvm_init_maxwellian", "dvm_step",
     "dvm_dt", "dvm_global_sums", "dvm_current_f", "dvm_moments", "dvm_check", "dvm_f_to_canonical", "dvm_f_from_canonical",
-    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_engine", "dvm_tune_split",
+    "dvm_destroy_solver", "dvm_tune_shapes", "dvm_tune_set", "dvm_tune_get", "dvm_tune_split",
     "dvm_batch_create", "dvm_batch_workspace_bytes", "dvm_batch_bind", "dvm_batch_step", "dvm_batch_tune",
     "dvm_batch_info", "dvm_destroy_batch",
     "dvm_features", "dvm_labels", "dvm_mlp_create", "dvm_mlp_workspace_bytes", "dvm_mlp_bind",
@@ -113,7 +113,6 @@ def lib():
         L.dvm_tune_shapes.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_tune_set.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dvm_tune_get.argtypes = [P, P, P, P, P]
-        L.dvm_tune_engine.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_tune_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
         L.dvm_destroy_solver.argtypes = [P]
         L.dvm_destroy_solver.restype = None
@@ -407,12 +406,6 @@ class Solver:
 
     def set_shape(self, threads, wpe, xcd_group=1, nt_store=0):
         _check(lib().dvm_tune_set(self.h, int(threads), int(wpe), int(xcd_group), int(nt_store)), "dvm_tune_set")
-
-    def engine(self, engine=-1):
-        """select the engine (0 fused, 1 deferred collision); returns the previous one"""
-        prev = C.c_int32(0)
-        _check(lib().dvm_tune_engine(self.h, int(engine), C.byref(prev)), "dvm_tune_engine")
-        return int(prev.value)
 
     def split(self, enable=-1, threads_irr=0, wpe_irr=0):
         """cells without FINER or WALL faces in a reduced kernel (1) or every

@@ -51,22 +51,20 @@ def oracle_run(case, steps):
     return dict(f=s.get_f(), mom=s.moments(), dt=dt, rc=rc, input=t["input"], sums=s.global_sums())
 
 
-def gpu_solver(case, precision, engine=None):
+def gpu_solver(case, precision):
     dm = D.Mesh(case.forest, case.solid)
     t = dm.tables()
     p = D.make_params(case.nv, case.vmax, precision=precision, scheme=case.scheme, collision=case.collision,
                       tau_mode=case.tau_mode, tau_or_kn=case.tau, inflow=case.inflow, t_wall=case.t_wall,
                       korobov_p=case.korobov_p)
     s = D.Solver(dm, p)
-    if engine is not None:
-        s.engine(engine)
     s.init_maxwellian(prim_for(case, t["input"]))
     return dm, s
 
 
-def gpu_run(case, steps, precision, engine=None):
+def gpu_run(case, steps, precision):
     import torch
-    dm, s = gpu_solver(case, precision, engine)
+    dm, s = gpu_solver(case, precision)
     dt = s.dt(case.cfl)
     s.step(steps, dt=dt)
     torch.cuda.synchronize()

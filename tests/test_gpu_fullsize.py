@@ -1,6 +1,6 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
 configuration the benchmark times (FP32 f, default kernel shape, fused
-engine, one step + global sums per step), on sampled cells; and the FP64
+kernel, one step + global sums per step), on sampled cells; and the FP64
 path at the paper-scale size with 20 % of the roots refined (139 GB of f).
 
 The oracle cannot hold 1e6 cells x 24^3 velocities in FP64, but eq. 2

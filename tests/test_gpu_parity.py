@@ -32,12 +32,12 @@ def sums_errors(g, ref, mom_ref):
     return np.abs(np.asarray(g) - ref) / scale
 
 
-def _compare(case, steps, precision, tol, f_tol=None, engine=None):
+def _compare(case, steps, precision, tol, f_tol=None):
     """moments (and the step's own moments buffer), the global sums reported
     by dvm_check and f against the oracle.  FP32 storage: f within 2e-5 of
     max |f| unless f_tol says otherwise."""
     o = oracle_run(case, steps)
-    g = gpu_run(case, steps, precision, engine)
+    g = gpu_run(case, steps, precision)
     assert o["rc"] == 0 and g["rc"] == 0
     assert g["dt"] == pytest.approx(o["dt"], rel=1e-15)
     err = moment_errors(g["mom"], o["mom"])
@@ -59,9 +59,8 @@ def _compare(case, steps, precision, tol, f_tol=None, engine=None):
     return o, g
 
 
-@pytest.mark.parametrize("engine", [0, 1])
-def test_uniform16_v8_fp64_20_steps(engine):
-    _compare(_uniform16_v8(), 20, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL, engine=engine)
+def test_uniform16_v8_fp64_20_steps():
+    _compare(_uniform16_v8(), 20, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
 
 
 def test_uniform16_v8_fp32_20_steps():
@@ -82,13 +81,12 @@ def test_octree_collision_modes_fp64(coll):
     _compare(case, 6, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
 
 
-@pytest.mark.parametrize("engine", [0, 1])
-def test_octree_inflow_outflow_wall_fp64(engine):
+def test_octree_inflow_outflow_wall_fp64():
     bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.WALL, I.OUTFLOW, I.OUTFLOW)
     f = balanced(I.random_forest(3, (2, 2, 2), 3, 0.2, bc))
     case = Case(f, 8, 6.0, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, 1.3, 0.1, 0.0, 1.1), t_wall=0.9,
                 fields="sines", field_args={"seed": 9})
-    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL, engine=engine)
+    _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
 
 
 def test_sphere_solid_inflow_fp64():
@@ -100,15 +98,14 @@ def test_sphere_solid_inflow_fp64():
     _compare(case, 8, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
 
 
-@pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("nv,vmax", [(12, 6.0), (16, 6.0), (24, 6.0)])
-def test_octree_sod_hard_sphere(nv, vmax, engine):
+def test_octree_sod_hard_sphere(nv, vmax):
     """the paper-scale construction (roots refined once at random, Sod-like jump,
     tau from Kn) on 4^3 roots: FP64 to 1e-12, FP32 to 2e-5 after 20 steps"""
     f = I.random_root_refinement((4, 4, 4), 0.4, 3)
     case = Case(f, nv, vmax, tau_mode=I.TAU_HS, tau=0.01, fields="sod_x")
-    o, g = _compare(case, 20, D.PREC_FP32, FP32_TOL, engine=engine)
-    g64 = gpu_run(case, 20, D.PREC_FP64, engine)
+    o, g = _compare(case, 20, D.PREC_FP32, FP32_TOL)
+    g64 = gpu_run(case, 20, D.PREC_FP64)
     err = moment_errors(g64["mom"], o["mom"])
     assert np.all(err <= FP64_TOL), err
     ef = np.abs(g64["f"] - o["f"]).max() / np.abs(o["f"]).max()
@@ -160,28 +157,6 @@ def test_canonical_roundtrip_and_nonphysical_flag():
     rc, sums, bad, n = s.check()
     assert rc == D.ERR_NONPHYSICAL and bad
     torch.cuda.synchronize()
-
-
-def test_engines_agree_and_switch_midway():
-    """fused and deferred-collision engines compute the same step; switching
-    engines between steps converts the stored state without changing it"""
-    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)
-    f = balanced(I.random_forest(6, (2, 2, 2), 3, 0.2, bc))
-    case = Case(f, 8, 6.0, tau_mode=I.TAU_HS, tau=0.03, inflow=(1.0, 0.8, 0.0, 0.1, 1.0), t_wall=1.2,
-                fields="sines", field_args={"seed": 21})
-    a = gpu_run(case, 6, D.PREC_FP64, engine=0)
-    b = gpu_run(case, 6, D.PREC_FP64, engine=1)
-    dm, s = gpu_solver(case, D.PREC_FP64, engine=1)
-    s.step(3, cfl=case.cfl)
-    s.engine(0)
-    s.step(2, cfl=case.cfl)
-    s.engine(1)
-    s.step(1, cfl=case.cfl)
-    c = s.f_canonical().cpu().numpy()
-    scale = np.abs(a["f"]).max()
-    assert np.abs(a["f"] - b["f"]).max() <= 1e-13 * scale
-    assert np.abs(c - a["f"]).max() <= 1e-13 * scale
-    assert np.abs(a["mom"] - b["mom"]).max() <= 1e-13 * np.abs(a["mom"]).max()
 
 
 # --- MUSCL-minmod (the oracle's reading of the reconstruction) -------------

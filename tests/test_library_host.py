@@ -126,9 +126,8 @@ def test_solver_argument_errors_host_only():
     D.lib().dvm_destroy_solver(h)
 
 
-def test_muscl_solver_workspace_and_engine_host_only():
-    """MUSCL adds three face-value planes to the workspace and is a
-    fused-engine scheme: asking for the deferred-collision engine is refused"""
+def test_muscl_solver_workspace_host_only():
+    """MUSCL adds three face-value planes to the workspace"""
     import ctypes as C
     m = D.Mesh(I.uniform_forest((1, 1, 1), 2))
     sizes = {}
@@ -139,10 +138,6 @@ def test_muscl_solver_workspace_and_engine_host_only():
         sz = D.Sizes()
         assert D.lib().dvm_buffer_sizes(h, C.byref(sz)) == D.OK
         sizes[scheme] = (sz.f_bytes, sz.ws_bytes)
-        prev = C.c_int32()
-        rc = D.lib().dvm_tune_engine(h, 1, C.byref(prev))
-        assert prev.value == 0
-        assert rc == (D.ERR_UNSUPPORTED if scheme == D.SCHEME_MUSCL else D.OK)
         D.lib().dvm_destroy_solver(h)
     fb = sizes[D.SCHEME_UPWIND1][0]
     assert sizes[D.SCHEME_MUSCL][1] == sizes[D.SCHEME_UPWIND1][1] + 3 * fb
