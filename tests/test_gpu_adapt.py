@@ -191,3 +191,29 @@ def test_no_flags_is_identity_and_adapted_mesh_steps_like_the_oracle():
     assert np.all(moment_errors(s2.moments().cpu().numpy(), o["mom"]) <= 1e-12)
     fo = o["f"]
     assert np.abs(s2.f_canonical().cpu().numpy() - fo).max() <= 1e-12 * np.abs(fo).max()
+
+
+@pytest.mark.parametrize("precision", [D.PREC_FP64, D.PREC_FP32])
+def test_refine_everywhere_then_coarsen_back_is_the_identity(precision):
+    """refining every leaf copies its row into 8 children; coarsening every
+    complete sibling set back takes their mean, of identical rows: the
+    original leaf list and state (the 2:1 rule holds at every stage).  The
+    mean is summed in FP64: exact for FP32 rows (bitwise), within one
+    rounding per addition for FP64 rows"""
+    import torch
+    f0 = _sorted_forest(balanced(I.random_forest(5, (2, 2, 2), 2, 0.3)))
+    dm, s = _solver(f0, precision=precision)
+    s.init_maxwellian(I.fields("sines", I.leaf_centres(f0), seed=5))
+    s.step(2, cfl=0.5)
+    torch.cuda.synchronize()
+    x0 = s.f_canonical().cpu().numpy()
+    f1, m1, s1 = D.adapt(s, np.ones(s.n, np.int8))
+    assert s1.n == 8 * s.n and np.array_equal(np.sort(f1.level), np.sort(np.repeat(f0.level + 1, 8)))
+    f2, m2, s2 = D.adapt(s1, -np.ones(s1.n, np.int8))
+    assert np.array_equal(f2.level, f0.level) and np.array_equal(f2.ijk, f0.ijk)
+    torch.cuda.synchronize()
+    x2 = s2.f_canonical().cpu().numpy()
+    if precision == D.PREC_FP32:
+        assert np.array_equal(x2, x0)
+    else:
+        assert np.abs(x2 - x0).max() <= 4e-16 * np.abs(x0).max()
