@@ -294,3 +294,33 @@ def test_xcd_grouping_is_bitwise_neutral_with_ragged_tail(scheme):
             ref = out
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), g
+
+
+@pytest.mark.parametrize("nv,precision", [(24, D.PREC_FP64), (24, D.PREC_FP32), (16, D.PREC_FP64),
+                                          (12, D.PREC_FP32)])
+def test_every_compiled_shape_matches_oracle(nv, precision):
+    """Every step-kernel shape compiled for the grid (threads per workgroup,
+    waves per EU; some leave lanes idle in their last velocity round), with
+    and without non-temporal stores, on an octree with FINER, COARSER, wall
+    and inflow faces: f and the moments against the oracle after 3 steps"""
+    import torch
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)
+    f = balanced(I.random_forest(14, (2, 2, 2), 2, 0.3, bc))
+    case = Case(f, nv, 6.0, tau_mode=I.TAU_HS, tau=0.05, inflow=(1.0, 0.9, 0.0, 0.1, 1.0), t_wall=1.1,
+                fields="sines", field_args={"seed": 14})
+    o = oracle_run(case, 3)
+    dm, s = gpu_solver(case, precision)
+    prim = prim_for(case, dm.tables()["input"])
+    tol = FP64_TOL if precision == D.PREC_FP64 else FP32_TOL
+    shapes = s.shapes()
+    assert len(shapes) >= 1
+    for (t, w) in shapes:
+        for nt in (0, 1):
+            s.set_shape(t, w, 64, nt)
+            s.init_maxwellian(prim)
+            s.step(3, dt=o["dt"])
+            torch.cuda.synchronize()
+            fg = s.f_canonical().double().cpu().numpy()
+            em = moment_errors(s.moments().cpu().numpy(), o["mom"])
+            ef = np.abs(fg - o["f"]).max() / np.abs(o["f"]).max()
+            assert np.all(em <= tol) and ef <= tol, (t, w, nt, em, ef)
