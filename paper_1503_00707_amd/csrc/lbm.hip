@@ -43,12 +43,23 @@ __device__ constexpr Lattice<Q> kLat{};
 
 __device__ __forceinline__ int face_kind(uint32_t meta, int f) { return int((meta >> (3 * f)) & 7u); }
 
-template <typename F, int Q>
+// BUF: the state fits 32-bit byte offsets, so every access is a raw buffer
+// access (per-lane 32-bit cell offset, the population's base as a scalar
+// offset) instead of a 64-bit address per lane
+template <typename F, int Q, bool BUF>
 __global__ __launch_bounds__(256) void k_lbm(LbmArgs a) {
     const int64_t c = int64_t(impl::remap_cell(blockIdx.x, gridDim.x, a.xcd_log2)) * 256 + threadIdx.x;
     if (c >= a.n) return;
     const F *fi = static_cast<const F *>(a.f_in);
     F *fo = static_cast<F *>(a.f_out);
+    const uint32_t bytes = BUF ? uint32_t(uint64_t(Q) * uint64_t(a.n) * sizeof(F)) : 0u;
+    const impl::Rsrc ri = impl::rsrc(fi, bytes), ro = impl::rsrc(fo, bytes);
+    auto ld = [&](int q, int64_t idx) -> F {
+        if constexpr (BUF)
+            return impl::bld<F>(ri, uint32_t(idx) * uint32_t(sizeof(F)), uint32_t(q) * uint32_t(a.n) * uint32_t(sizeof(F)));
+        else
+            return fi[q * a.n + idx];
+    };
     const LbmCell rec = a.cells[c];
     const double h = a.h0 / double(1u << (rec.meta >> 24));
     const F r = F(a.dt / h);
@@ -66,7 +77,7 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs a) {
     double rho = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const F own = fi[q * n + c];
+        const F own = ld(q, c);
         F acc = F(0);
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
@@ -76,10 +87,10 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs a) {
             const int kind = face_kind(rec.meta, f);
             F up;
             if (kind == DVM_FACE_SAME || kind == DVM_FACE_COARSER) {
-                up = fi[q * n + rec.nb[f]];
+                up = ld(q, rec.nb[f]);
             } else if (kind == DVM_FACE_FINER) {
                 const int32_t *t = a.fine + fine_at[f];
-                up = F(0.25) * ((fi[q * n + t[0]] + fi[q * n + t[1]]) + (fi[q * n + t[2]] + fi[q * n + t[3]]));
+                up = F(0.25) * ((ld(q, t[0]) + ld(q, t[1])) + (ld(q, t[2]) + ld(q, t[3])));
             } else {
                 up = own;  // outflow: zero gradient
             }
@@ -101,7 +112,10 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs a) {
         const double feq = kLat<Q>.w[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         const double v = double(fs[q]);
         const double out = a.euler ? v + a.relax * (feq - v) : feq + (v - feq) * a.relax;
-        fo[q * n + c] = F(out);
+        if constexpr (BUF)
+            impl::bst<F, 0>(ro, uint32_t(c) * uint32_t(sizeof(F)), uint32_t(q) * uint32_t(n) * uint32_t(sizeof(F)), F(out));
+        else
+            fo[q * n + c] = F(out);
     }
 }
 
@@ -179,7 +193,12 @@ hipError_t run(const char *what, const LbmArgs &a, const void *p0, void *p1, dou
                double h0, int flagmode, hipStream_t st) {
     const dim3 g{unsigned((n + 255) / 256), 1, 1}, blk{256, 1, 1};
     switch (what[0]) {
-    case 's': hipLaunchKernelGGL((k_lbm<F, Q>), g, blk, 0, st, a); break;
+    case 's':
+        if (uint64_t(Q) * uint64_t(n) * sizeof(F) < (uint64_t(1) << 32))
+            hipLaunchKernelGGL((k_lbm<F, Q, true>), g, blk, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_lbm<F, Q, false>), g, blk, 0, st, a);
+        break;
     case 'm':
         hipLaunchKernelGGL((k_lbm_moments<F, Q>), g, blk, 0, st, static_cast<const F *>(p0), a.cells, n, h0, p2, p3);
         break;
