@@ -381,7 +381,7 @@ __device__ inline void relax_store(const MaxwellSmem<F, NH> &sm, const Regs<F, N
     for (int q = 0; q < L::S; ++q) {
         if (!ln.ok(q)) continue;
         int a3[3];
-        ln.axes(q, a3[0], a3[1], a3[2]);
+        ln.axes_late(q, a3[0], a3[1], a3[2]);  // recomputed: nothing held across the step for it
         F G[3][2], P[3][2];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
