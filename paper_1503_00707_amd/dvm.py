@@ -88,6 +88,11 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1503_00707_amd.build`")
+        # torch first: the library then resolves its HIP runtime to the one
+        # torch loaded (same soname), so the streams and device buffers torch
+        # hands over belong to the runtime that launches the kernels; loaded
+        # first, it would bring a second runtime into the process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.dvm_last_error.restype = C.c_char_p

@@ -242,3 +242,17 @@ def test_korobov_solver_arguments_host_only():
         p = D.make_params(nv, 4.5, collision=D.COLL_KOROBOV, tau_or_kn=0.5, **kw)
         h = __import__("ctypes").c_void_p()
         assert D.lib().dvm_create_solver(m.h, __import__("ctypes").byref(p), __import__("ctypes").byref(h)) == code
+
+
+def test_one_hip_runtime_in_the_process():
+    """the library shares torch's HIP runtime: after loading it, exactly one
+    HIP runtime is mapped, whichever of the two was asked for first (streams
+    and events handed over by torch belong to the runtime that launches)"""
+    import subprocess
+    import sys
+    code = ("from paper_1503_00707_amd import dvm as D; D.lib(); import torch; "
+            "print(sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__)))).stdout
+    libs = eval(out.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
