@@ -177,10 +177,16 @@ def gpu_bench(args, precision=None, steps=None, warmup=None, keep_samples=True, 
     achieved = alg_bytes / k_mean_s / 1e9
     drift = np.abs(g1 - g0) / np.maximum(np.abs(g0), 1e-300)
     split = s.split() == 1 and w.scheme == I.SCHEME_UPWIND1
-    kernel = ("k_step fused step (transport+moments+Maxwellian+BGK) as two launches: the reduced kernel over "
-              "cells without FINER/WALL faces, the full kernel over the rest; events bracket both"
-              if split else "k_step (fused transport+moments+Maxwellian+BGK, one launch; cells without FINER/WALL "
-              "faces take the reduced code path)")
+    if w.scheme == I.SCHEME_MUSCL:
+        kernel = ("k_step MUSCL (face values reconstructed in the step from two face hops per axis, then "
+                  "moments+Maxwellian+BGK, one launch; cells whose stencil values are single rows take the "
+                  "branch-free code path)")
+    elif split:
+        kernel = ("k_step fused step (transport+moments+Maxwellian+BGK) as two launches: the reduced kernel over "
+                  "cells without FINER/WALL faces, the full kernel over the rest; events bracket both")
+    else:
+        kernel = ("k_step (fused transport+moments+Maxwellian+BGK, one launch; cells without FINER/WALL "
+                  "faces take the reduced code path)")
     del s, mesh
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

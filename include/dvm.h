@@ -75,8 +75,8 @@ extern "C" {
 #define DVM_PREC_FP64 0         /* f stored and transported in FP64 */
 #define DVM_PREC_FP32 1         /* f in FP32; moments, Maxwellian, correction in FP64 */
 #define DVM_SCHEME_UPWIND1 0
-#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction (the workspace
-                                   then also holds 3 face-value planes) */
+#define DVM_SCHEME_MUSCL 1      /* minmod-limited linear reconstruction, formed inside the
+                                   step from two face hops per axis (no extra buffers) */
 #define DVM_COLL_EXP 0          /* f' = Mt + (f* - Mt) exp(-dt/tau) */
 #define DVM_COLL_EULER 1        /* f' = f* + dt/tau (Mt - f*) */
 #define DVM_COLL_OFF 2          /* f' = f* */
@@ -135,7 +135,7 @@ typedef struct {
     size_t f_bytes;           /* one state buffer; two are bound (ping-pong) */
     size_t moments_bytes;     /* FP64 [5][n_cells] */
     size_t tables_bytes;      /* device mesh tables */
-    size_t ws_bytes;          /* ghost tables, flags, reduction partials, MUSCL face values,
+    size_t ws_bytes;          /* ghost tables, flags, reduction partials, selection list,
                                  hybrid masks and flux records, Korobov trial table */
     int64_t n_cells;
     int64_t nv_total;         /* N^3 */

@@ -34,7 +34,7 @@ struct StepArgs {
     int tau_mode;            // DVM_TAU_*
     double tau_or_kn;
     int xcd_log2;            // runs of 2^xcd_log2 consecutive cells kept on one XCD
-    const void *face;        // MUSCL face values [3][n_cells][NV] (NULL: first order)
+    int muscl;               // 1: MUSCL-minmod transport (reconstructed in the step), 0: first order
     const uint32_t *sel;     // the cells this launch steps, one per workgroup (NULL: 0 .. n_cells-1)
     int64_t n_sel;           // their number (used when sel is set)
 };
@@ -61,7 +61,6 @@ struct StepConfig {
 // All return hipError_t of the launch (hipErrorInvalidValue: no kernel for N).
 hipError_t launch_step(bool fp64, const StepArgs &a, const StepConfig &cfg, hipStream_t st);
 hipError_t launch_init(bool fp64, const InitArgs &a, hipStream_t st);
-hipError_t launch_face(bool fp64, const StepArgs &a, hipStream_t st);
 hipError_t launch_moments(bool fp64, const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st);
 hipError_t launch_wall_den(bool fp64, const void *m1, double *den, const VelGrid &g, hipStream_t st);
 hipError_t launch_global_sums(const double *mom, const DevCell *cells, int64_t n, double h0, double *partials,
@@ -177,7 +176,6 @@ hipError_t launch_lbm_canon(int q, bool fp64, const void *src, void *dst, int64_
     hipError_t launch_step_batch_##SUF(const StepArgs *inst, const uint32_t *wg_end, int n_inst,         \
                                        uint32_t total_wg, int nh, const StepConfig &cfg, hipStream_t st); \
     hipError_t launch_init_##SUF(const InitArgs &a, hipStream_t st);                                     \
-    hipError_t launch_face_##SUF(const StepArgs &a, hipStream_t st);                                     \
     hipError_t launch_moments_##SUF(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st); \
     hipError_t launch_wall_den_##SUF(const void *m1, double *den, const VelGrid &g, hipStream_t st);
 DVM_DECLARE_PREC(f32)

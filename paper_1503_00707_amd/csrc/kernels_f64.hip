@@ -11,7 +11,6 @@ hipError_t launch_step_batch_f64(const StepArgs *inst, const uint32_t *wg_end, i
     return impl::step_batch_dispatch<double>(inst, wg_end, n_inst, total_wg, nh, cfg, st);
 }
 hipError_t launch_init_f64(const InitArgs &a, hipStream_t st) { return impl::init_dispatch<double>(a, st); }
-hipError_t launch_face_f64(const StepArgs &a, hipStream_t st) { return impl::face_dispatch<double>(a, st); }
 hipError_t launch_moments_f64(const void *f, double *out, int64_t n, const VelGrid &g, hipStream_t st) {
     return impl::moments_dispatch<double>(f, out, n, g, st);
 }

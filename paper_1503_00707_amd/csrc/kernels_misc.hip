@@ -118,10 +118,6 @@ hipError_t launch_global_sums_batch(const SumArgs *inst, int n_inst, int n_part,
     return hipGetLastError();
 }
 
-hipError_t launch_face(bool fp64, const StepArgs &a, hipStream_t st) {
-    return fp64 ? launch_face_f64(a, st) : launch_face_f32(a, st);
-}
-
 hipError_t launch_init(bool fp64, const InitArgs &a, hipStream_t st) {
     return fp64 ? launch_init_f64(a, st) : launch_init_f32(a, st);
 }

@@ -108,18 +108,14 @@ std::string key_text(const TuneKey &k, const std::string &arch) {
     return o.str();
 }
 
-// the solver's trial step: reads f[cur], writes f[cur ^ 1], the moments and
-// (MUSCL) the face planes; the state it advances is unchanged
+// the solver's trial step: reads f[cur], writes f[cur ^ 1] and the moments;
+// the state it advances is unchanged
 hipError_t trial_step(const dvm_solver *s, const StepConfig &cfg, double dt, hipStream_t st) {
     StepArgs a = solver_step_args(s, dt);
     a.xcd_log2 = 0;
     while ((1 << (a.xcd_log2 + 1)) <= cfg.xcd_group) ++a.xcd_log2;
     a.f_in = s->f[s->cur];
     a.f_out = s->f[s->cur ^ 1];
-    if (s->muscl) {
-        hipError_t e = launch_face(s->fp64, a, st);
-        if (e != hipSuccess) return e;
-    }
     return launch_step(s->fp64, a, cfg, st);
 }
 

@@ -38,7 +38,7 @@ StepArgs dvm::solver_step_args(const dvm_solver *s, double dt) {
     a.tau_or_kn = s->p.tau_or_kn;
     a.xcd_log2 = 0;
     while ((1 << (a.xcd_log2 + 1)) <= s->cfg.xcd_group) ++a.xcd_log2;
-    a.face = s->face();
+    a.muscl = s->muscl ? 1 : 0;
     return a;
 }
 
@@ -146,8 +146,6 @@ int dvm_create_solver(const dvm_mesh *m, const dvm_params *p, dvm_solver **out) 
     s->off_part = o; o += align256(size_t(kPartials) * 5 * 8);
     s->off_sums = o; o += 256;
     s->muscl = p->scheme == DVM_SCHEME_MUSCL;
-    s->off_face = o;
-    if (s->muscl) o += 3 * s->f_bytes;
     s->off_kor = o;
     if (p->collision == DVM_COLL_KOROBOV) {
         s->kor_p = p->korobov_p;
@@ -321,10 +319,6 @@ int dvm_step(dvm_solver *s, int32_t n_steps, double dt, double cfl, void *stream
     for (int it = 0; it < n_steps; ++it) {
         a.f_in = s->f[s->cur];
         a.f_out = s->f[s->cur ^ 1];
-        if (s->muscl) {
-            e = launch_face(s->fp64, a, st);
-            if (e != hipSuccess) return hip_fail(e, "MUSCL face values");
-        }
         if (use_split(s)) {
             StepArgs ar = a;
             ar.sel = s->sel();

@@ -36,7 +36,6 @@ struct dvm_solver {
     size_t f_bytes = 0, mom_bytes = 0, tab_bytes = 0, ws_bytes = 0;
     // workspace sections (byte offsets)
     size_t off_gin = 0, off_m1 = 0, off_den = 0, off_flag = 0, off_part = 0, off_sums = 0;
-    size_t off_face = 0;         // MUSCL face values [3][n][NV] (0 bytes for first order)
     size_t off_kor = 0;          // Korobov collision: trial table [p][NV] (64-bit entries)
     std::vector<uint64_t> kor_host;
     int64_t kor_p = 0, kor_a = 0;
@@ -66,7 +65,6 @@ struct dvm_solver {
     dvm::StepConfig cfg_irr{};     // shape of the launch over the other cells
 
     void *gin() const { return ws + off_gin; }
-    void *face() const { return muscl ? ws + off_face : nullptr; }
     void *m1() const { return ws + off_m1; }
     const uint64_t *kor() const { return reinterpret_cast<const uint64_t *>(ws + off_kor); }
     bool korobov() const { return p.collision == DVM_COLL_KOROBOV; }

@@ -418,6 +418,30 @@ __device__ inline void octant_sums(const F (&v)[8][S], int q, double &s0, double
     sz = q1 - q0;
 }
 
+// Per-thread FP64 partial sums (1, xi, |xi|^2/2) f over the thread's slots.
+template <typename F, int NH, int T>
+__device__ __forceinline__ void add_moments(const Regs<F, NH, T> &fo, const VelGrid &g, double (&m)[5]) {
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    const L ln;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        if (!ln.ok(q)) continue;
+        int a3[3];
+        ln.axes_late(q, a3[0], a3[1], a3[2]);
+        const double xa = (a3[0] + 0.5) * g.dv[0];
+        const double ya = (a3[1] + 0.5) * g.dv[1];
+        const double za = (a3[2] + 0.5) * g.dv[2];
+        double s0, sx, sy, sz;
+        octant_sums<F, S>(fo, q, s0, sx, sy, sz);
+        m[0] += s0;
+        m[1] += xa * sx;
+        m[2] += ya * sy;
+        m[3] += za * sz;
+        m[4] += 0.5 * (xa * xa + ya * ya + za * za) * s0;
+    }
+}
+
 template <typename F, int NH, int T>
 struct StepSmem {
     static constexpr int NW = (T + 63) / 64;
@@ -436,11 +460,10 @@ struct StepSmem {
 // WALL faces are given an empty descriptor there (reads return 0); the
 // correction pass then adds nu * f_up for them, f_up the mean of the four
 // finer rows or rho_w times the wall Maxwellian.
-template <typename F, int NH, int T, bool OCT_FENCE, bool MU, bool REG, bool LATE_OWN>
+template <typename F, int NH, int T, bool OCT_FENCE, bool REG, bool LATE_OWN>
 __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &cell, const Rsrc (&R1)[6],
-                                          const Rsrc (&RD)[3], const Rsrc &own, const F *fin, const F *face,
-                                          const StepArgs &a, const double *rho_w, double dth, double (&m)[5],
-                                          float *stage) {
+                                          const Rsrc &own, const F *fin, const StepArgs &a, const double *rho_w,
+                                          double dth, double (&m)[5], float *stage) {
     using L = Lane<NH, T>;
     constexpr int S = L::S;
     constexpr int64_t NV = 8 * L::B;
@@ -467,15 +490,7 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
             const F ux = bld<F>(R1[fx], voff, so);
             const F uy = bld<F>(R1[fy], voff, so);
             const F uz = bld<F>(R1[fz], voff, so);
-            // the value leaving through the downwind face: the cell average
-            // (first order) or its MUSCL face value
-            F dx = v, dy = v, dz = v;
-            if (MU) {
-                dx = bld<F>(RD[0], voff, so);
-                dy = bld<F>(RD[1], voff, so);
-                dz = bld<F>(RD[2], voff, so);
-            }
-            fo[o][q] = v - (nu[0][q] * (dx - ux) + nu[1][q] * (dy - uy) + nu[2][q] * (dz - uz));
+            fo[o][q] = v - (nu[0][q] * (v - ux) + nu[1][q] * (v - uy) + nu[2][q] * (v - uz));
         }
         // bound the look-ahead of the scheduler to one octant: hoisting loads
         // further only trades them for spills
@@ -496,7 +511,7 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int64_t nb = cell.nbr_rt(f, k);
-                r[k] = rsrc(MU ? face + (int64_t(b) * a.n_cells + nb) * NV : fin + nb * NV, kRow);
+                r[k] = rsrc(fin + nb * NV, kRow);
             }
             sc = F(0.25);
         } else {
@@ -549,22 +564,299 @@ __device__ __forceinline__ void transport(Regs<F, NH, T> &fo, const CellView &ce
         }
         }
     }
+    add_moments<F, NH, T>(fo, a.g, m);
+}
+
+// ---------------------------------------------------------------------------
+// MUSCL-minmod transport inside the step (no face-value buffers).  The paper
+// is silent on the reconstruction; the reading: per cell x, axis b and
+// velocity, sigma = minmod((f - fm)/dm, (fp - f)/dp), fm and fp the low- and
+// high-side face-neighbour values -- the neighbour's average (SAME, COARSER),
+// the mean of the four finer leaves (FINER), the inflow ghost (INFLOW) or the
+// cell's own value (OUTFLOW) -- and dm, dp the centre distances h, 3h/4
+// (FINER), 3h/2 (COARSER); sigma = 0 in a cell that touches a wall.  The value
+// a cell lets through the face its velocity leaves by is
+//   D = f + sgn(xi_b) (h/2) sigma_b,
+// the cell's own outflow on that face and its downwind neighbour's inflow.  A
+// step therefore reads, per octant and axis, the cell's two face neighbours
+// (its own slope) and, behind its upwind neighbour, that neighbour's far
+// neighbour (the upwind slope): two hops along each axis.
+// ---------------------------------------------------------------------------
+
+template <typename F>
+__device__ __forceinline__ F minmod(F l, F r) {
+    return l * r <= F(0) ? F(0) : (fabs(l) < fabs(r) ? l : r);
+}
+
+// A cell record read word by word through scalar loads (a neighbour's, used
+// for a few fields only).
+struct RecRT {
+    cuint32_t *p;
+    __device__ __forceinline__ RecRT(const DevCell *cells, int64_t x)
+        : p(as_const_space(reinterpret_cast<const uint32_t *>(cells + x))) {}
+    __device__ __forceinline__ int type(int f) const { return (p[24 + (f >> 2)] >> (8 * (f & 3))) & 0xff; }
+    __device__ __forceinline__ int32_t nbr(int f, int k) const { return int32_t(p[4 * f + k]); }
+    __device__ __forceinline__ int level() const { return (p[25] >> 16) & 0xff; }
+    __device__ __forceinline__ int flags() const { return p[25] >> 24; }
+};
+
+// Every face of the cell is SAME, INFLOW or OUTFLOW, and behind no SAME face
+// lies a FINER face: each value its MUSCL stencil reads is one row (the
+// branch-free code).
+__device__ __forceinline__ bool muscl_single_row(const DevCell *cells, int64_t c) {
+    const RecRT r(cells, c);
+    bool ok = true;
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-        if (!ln.ok(q)) continue;
-        int a3[3];
-        ln.axes_late(q, a3[0], a3[1], a3[2]);
-        const double xa = (a3[0] + 0.5) * a.g.dv[0];
-        const double ya = (a3[1] + 0.5) * a.g.dv[1];
-        const double za = (a3[2] + 0.5) * a.g.dv[2];
-        double s0, sx, sy, sz;
-        octant_sums<F, S>(fo, q, s0, sx, sy, sz);
-        m[0] += s0;
-        m[1] += xa * sx;
-        m[2] += ya * sy;
-        m[3] += za * sz;
-        m[4] += 0.5 * (xa * xa + ya * ya + za * za) * s0;
+    for (int f = 0; f < 6; ++f) {
+        const int ty = r.type(f);
+        if (ty == DVM_FACE_SAME) ok &= RecRT(cells, r.nbr(f, 0)).type(f) != DVM_FACE_FINER;
+        else ok &= ty == DVM_FACE_INFLOW || ty == DVM_FACE_OUTFLOW;
     }
+    return ok;
+}
+
+// Value of cell x's face neighbour across face f for the thread's slots of
+// octant o (mean of the rows of a FINER face), and 1 / centre distance.
+// own: x's values (the OUTFLOW side).
+template <typename F, int NH, int T>
+__device__ __forceinline__ void muscl_side(const StepArgs &a, const RecRT &x, double h, int f, int o,
+                                           const F (&own)[Lane<NH, T>::S], F (&out)[Lane<NH, T>::S], F &inv) {
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    constexpr int64_t NV = 8 * L::B;
+    constexpr uint32_t kRow = uint32_t(NV * sizeof(F));
+    const F *fin = static_cast<const F *>(a.f_in);
+    const uint32_t voff = threadIdx.x * sizeof(F);
+    const int ty = x.type(f);
+    if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER || ty == DVM_FACE_INFLOW) {
+        const Rsrc r = rsrc(ty == DVM_FACE_INFLOW ? static_cast<const F *>(a.ghost_in) : fin + int64_t(x.nbr(f, 0)) * NV,
+                            kRow);
+#pragma unroll
+        for (int q = 0; q < S; ++q) out[q] = bld<F>(r, voff, L::template soff<F>(o, q));
+        inv = F(1.0 / (ty == DVM_FACE_COARSER ? 1.5 * h : h));
+    } else if (ty == DVM_FACE_FINER) {
+        Rsrc r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = rsrc(fin + int64_t(x.nbr(f, k)) * NV, kRow);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint32_t so = L::template soff<F>(o, q);
+            out[q] = F(0.25) * (((bld<F>(r[0], voff, so) + bld<F>(r[1], voff, so)) + bld<F>(r[2], voff, so)) +
+                                bld<F>(r[3], voff, so));
+        }
+        inv = F(1.0 / (0.75 * h));
+    } else {  // OUTFLOW (WALL: the slope is zero anyway)
+#pragma unroll
+        for (int q = 0; q < S; ++q) out[q] = own[q];
+        inv = F(1.0 / h);
+    }
+}
+
+// D of cell x on axis b for the thread's slots of octant o, the velocity
+// component's sign bit sb (1: positive, the value at x's high face).
+template <typename F, int NH, int T>
+__device__ __forceinline__ void muscl_face_value(const StepArgs &a, int64_t x, int b, int sb, int o,
+                                                 F (&out)[Lane<NH, T>::S]) {
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    constexpr int64_t NV = 8 * L::B;
+    const F *fin = static_cast<const F *>(a.f_in);
+    const uint32_t voff = threadIdx.x * sizeof(F);
+    const RecRT r(a.cells, x);
+    const Rsrc row = rsrc(fin + x * NV, uint32_t(NV * sizeof(F)));
+    F fx[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) fx[q] = bld<F>(row, voff, L::template soff<F>(o, q));
+    if (r.flags() & 1) {
+#pragma unroll
+        for (int q = 0; q < S; ++q) out[q] = fx[q];
+        return;
+    }
+    const double h = a.h0 / double(1 << r.level());
+    F lo[S], hi[S], ilo, ihi;
+    muscl_side<F, NH, T>(a, r, h, 2 * b, o, fx, lo, ilo);
+    muscl_side<F, NH, T>(a, r, h, 2 * b + 1, o, fx, hi, ihi);
+    const F half = F(sb ? 0.5 * h : -0.5 * h);
+#pragma unroll
+    for (int q = 0; q < S; ++q) out[q] = fx[q] + half * minmod((fx[q] - lo[q]) * ilo, (hi[q] - fx[q]) * ihi);
+}
+
+// MUSCL transport of the thread's slots; fo holds f on entry (FAST with
+// LATE_OWN: loaded here, octant by octant) and f* on return.
+//   FAST: the cells of muscl_single_row: per face the neighbour row and the
+//         row behind the neighbour, selected once per cell; the loads of an
+//         octant are independent of each other and issued together;
+//   else: any cell (level jumps on either hop, walls): the stencil is read
+//         from the neighbours' records, axis by axis.
+template <typename F, int NH, int T, bool FAST, bool LATE_OWN>
+__device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellView &cell, int64_t c,
+                                                const Rsrc &own, const StepArgs &a, const double *rho_w, double dth,
+                                                double (&m)[5]) {
+    using L = Lane<NH, T>;
+    constexpr int S = L::S;
+    constexpr int64_t NV = 8 * L::B;
+    constexpr uint32_t kRow = uint32_t(NV * sizeof(F));
+    const L ln;
+    const uint32_t voff = threadIdx.x * sizeof(F);
+    const F *fin = static_cast<const F *>(a.f_in);
+    const double h = a.h0 / double(1 << cell.level());
+    const F hh = F(0.5 * h), ih = F(1.0 / h);
+    if constexpr (FAST) {
+        // per face f: the cell whose row lies across f (the inflow ghost: -1;
+        // an OUTFLOW face: the cell itself) and, behind a SAME neighbour u,
+        // the next one along the axis (u itself at an OUTFLOW or WALL face);
+        // 1/distance from u to that one; whether u has a slope (SAME and not
+        // touching a wall)
+        int32_t Ni[6], Fi[6];
+        uint32_t on = 0, farc = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int ty = cell.type(f);
+            Ni[f] = ty == DVM_FACE_SAME ? cell.nbr(f, 0) : ty == DVM_FACE_INFLOW ? -1 : int32_t(c);
+            Fi[f] = Ni[f];
+            if (ty == DVM_FACE_SAME) {
+                const RecRT u(a.cells, Ni[f]);
+                const int tu = u.type(f);
+                if (tu == DVM_FACE_SAME || tu == DVM_FACE_COARSER) Fi[f] = u.nbr(f, 0);
+                else if (tu == DVM_FACE_INFLOW) Fi[f] = -1;
+                on |= uint32_t(!(u.flags() & 1)) << f;
+                farc |= uint32_t(tu == DVM_FACE_COARSER) << f;
+            }
+        }
+        // descriptors and per-face factors made once, before the octant loop
+        // and without branches: a select inside the loop becomes a branch,
+        // and the compiler then hoists every octant's loads and spills them
+        const uint64_t ghost = reinterpret_cast<uint64_t>(a.ghost_in), base = reinterpret_cast<uint64_t>(fin);
+        const auto row = [&](int32_t i) {
+            const uint64_t at = base + uint64_t(int64_t(i < 0 ? 0 : i) * NV * int64_t(sizeof(F)));
+            return rsrc(reinterpret_cast<const void *>(i < 0 ? ghost : at), kRow);
+        };
+        const F i15 = F(1.0 / (1.5 * h));
+        Rsrc RN[6], RF[6];
+        F ifar[6], son[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            RN[f] = row(Ni[f]);
+            RF[f] = row(Fi[f]);
+            ifar[f] = (farc >> f) & 1u ? i15 : ih;
+            son[f] = (on >> f) & 1u ? F(1) : F(0);
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
+            F lo[3][S], hi[3][S], far[3][S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const uint32_t so = L::template soff<F>(o, q);
+                if constexpr (LATE_OWN) fo[o][q] = bld<F>(own, voff, so);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    lo[b][q] = bld<F>(RN[2 * b], voff, so);
+                    hi[b][q] = bld<F>(RN[2 * b + 1], voff, so);
+                    far[b][q] = bld<F>(RF[sg[b] ? 2 * b : 2 * b + 1], voff, so);  // a positive component enters through the low face
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                int a3[3];
+                ln.axes_late(q, a3[0], a3[1], a3[2]);
+                const F v = fo[o][q];
+                F t = F(0);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const int fu = sg[b] ? 2 * b : 2 * b + 1;
+                    const F half = sg[b] ? hh : -hh;
+                    const F dc = v + half * minmod((v - lo[b][q]) * ih, (hi[b][q] - v) * ih);
+                    const F up = sg[b] ? lo[b][q] : hi[b][q];
+                    const F su = sg[b] ? minmod((up - far[b][q]) * ifar[fu], (v - up) * ih)
+                                       : minmod((up - v) * ih, (far[b][q] - up) * ifar[fu]);
+                    const F din = up + half * (son[fu] * su);
+                    const F nub = F(dth) * (F(a3[b]) + F(0.5)) * F(a.g.dv[b]);
+                    t += nub * (dc - din);
+                }
+                fo[o][q] = v - t;
+            }
+            asm volatile("" ::: "memory");  // one octant's loads in flight at a time
+        }
+    } else {
+        // runtime loops over octants and axes (one copy of the code); the
+        // register arrays are reached through uniform selects, never indexed
+        F nu[3][S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            int a3[3];
+            ln.axes(q, a3[0], a3[1], a3[2]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) nu[b][q] = F(dth) * (F(a3[b]) + F(0.5)) * F(a.g.dv[b]);
+        }
+        const RecRT rc(a.cells, c);
+        const bool wall = cell.flags() & 1;
+#pragma nounroll
+        for (int o = 0; o < 8; ++o) {
+            F v[S], t[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                v[q] = fo[0][q];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) v[q] = o == k ? fo[k][q] : v[q];
+                t[q] = F(0);
+            }
+#pragma nounroll
+            for (int b = 0; b < 3; ++b) {
+                const int sb = (o >> (2 - b)) & 1;
+                const F half = sb ? hh : -hh;
+                F dc[S], in[S];
+                if (wall) {
+#pragma unroll
+                    for (int q = 0; q < S; ++q) dc[q] = v[q];
+                } else {
+                    F lo[S], hi[S], ilo, ihi;
+                    muscl_side<F, NH, T>(a, rc, h, 2 * b, o, v, lo, ilo);
+                    muscl_side<F, NH, T>(a, rc, h, 2 * b + 1, o, v, hi, ihi);
+#pragma unroll
+                    for (int q = 0; q < S; ++q) dc[q] = v[q] + half * minmod((v[q] - lo[q]) * ilo, (hi[q] - v[q]) * ihi);
+                }
+                const int fu = sb ? 2 * b : 2 * b + 1;  // a positive component enters through the low face
+                const int ty = rc.type(fu);
+                if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER || ty == DVM_FACE_FINER) {
+                    // one upwind cell, or four behind sub-faces of a quarter of the area each
+                    const int nk = ty == DVM_FACE_FINER ? 4 : 1;
+#pragma nounroll
+                    for (int k = 0; k < nk; ++k) {
+                        F x[S];
+                        muscl_face_value<F, NH, T>(a, rc.nbr(fu, k), b, sb, o, x);
+#pragma unroll
+                        for (int q = 0; q < S; ++q) in[q] = k == 0 ? x[q] : in[q] + x[q];
+                    }
+                    if (nk == 4) {
+#pragma unroll
+                        for (int q = 0; q < S; ++q) in[q] *= F(0.25);
+                    }
+                } else if (ty == DVM_FACE_INFLOW || ty == DVM_FACE_WALL) {
+                    const bool inflow = ty == DVM_FACE_INFLOW;
+                    const Rsrc r = rsrc(inflow ? a.ghost_in : a.wall_m1, kRow);
+                    const F sc = inflow ? F(1) : F(rho_w[fu]);
+#pragma unroll
+                    for (int q = 0; q < S; ++q) in[q] = sc * bld<F>(r, voff, L::template soff<F>(o, q));
+                } else {  // OUTFLOW: zero gradient
+#pragma unroll
+                    for (int q = 0; q < S; ++q) in[q] = v[q];
+                }
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const F nub = b == 0 ? nu[0][q] : b == 1 ? nu[1][q] : nu[2][q];
+                    t[q] += nub * (dc[q] - in[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const F r = v[q] - t[q];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) fo[k][q] = o == k ? r : fo[k][q];
+            }
+        }
+    }
+    add_moments<F, NH, T>(fo, a.g, m);
 }
 
 // A step-cell hook runs after the cell's own values are loaded and before
@@ -576,7 +868,8 @@ struct NoHook {
 };
 
 // One fused step of cell c by the calling workgroup.
-template <typename F, int NH, int T, int FENCE, bool NT, bool MU, bool REG = false, class Hook = NoHook>
+// MU: 0 first order, 1 MUSCL (any cell), 2 MUSCL (a cell of muscl_single_row).
+template <typename F, int NH, int T, int FENCE, bool NT, int MU, bool REG = false, class Hook = NoHook>
 __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem<F, NH, T> &sm,
                                           const Hook &hook = Hook()) {
     constexpr int B = NH * NH * NH;
@@ -640,32 +933,30 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
 
     hook.template apply<F, NH, T>(a, cell, c, fo, sm.red);
 
-    // one row descriptor per face for the main transport pass: the upwind
-    // cell's average (first order) or its downwind MUSCL face value
-    const F *face = static_cast<const F *>(a.face);
-    Rsrc R1[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        const int ty = cell.type(f);
-        const F *row = fin + c * NV;  // OUTFLOW: zero gradient
-        uint32_t bytes = kRow;
-        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) {
-            const int64_t nb = cell.nbr(f, 0);
-            row = MU ? face + ((f >> 1) * a.n_cells + nb) * NV : fin + nb * NV;
-        } else if (ty == DVM_FACE_INFLOW) {
-            row = static_cast<const F *>(a.ghost_in);
-        } else if (ty == DVM_FACE_FINER || ty == DVM_FACE_WALL) {
-            bytes = 0;  // added by the correction pass
-        }
-        R1[f] = rsrc(row, bytes);
-    }
-    Rsrc RD[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) RD[b] = rsrc(MU ? face + (b * a.n_cells + c) * NV : fin, MU ? kRow : 0u);
-
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    transport<F, NH, T, (FENCE != 0), MU, REG, kLateOwn>(fo, cell, R1, RD, own, fin, face, a, sm.rho_w, dth, m,
-                                                        &sm.stage[0][0][0]);
+    if constexpr (MU) {
+        transport_muscl<F, NH, T, MU == 2, kLateOwn>(fo, cell, c, own, a, sm.rho_w, dth, m);
+    } else {
+        // one row descriptor per face for the main transport pass: the upwind
+        // cell's average
+        Rsrc R1[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int ty = cell.type(f);
+            const F *row = fin + c * NV;  // OUTFLOW: zero gradient
+            uint32_t bytes = kRow;
+            if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) {
+                row = fin + int64_t(cell.nbr(f, 0)) * NV;
+            } else if (ty == DVM_FACE_INFLOW) {
+                row = static_cast<const F *>(a.ghost_in);
+            } else if (ty == DVM_FACE_FINER || ty == DVM_FACE_WALL) {
+                bytes = 0;  // added by the correction pass
+            }
+            R1[f] = rsrc(row, bytes);
+        }
+        transport<F, NH, T, (FENCE != 0), REG, kLateOwn>(fo, cell, R1, own, fin, a, sm.rho_w, dth, m,
+                                                         &sm.stage[0][0][0]);
+    }
     block_sum<T, 5>(m, sm.red);
 
     const double w = a.g.w;
@@ -720,20 +1011,25 @@ __device__ __forceinline__ bool needs_correction(const DevCell *cells, int64_t c
 }
 
 // One fused step, one cell per workgroup: every cell, or the cells listed in
-// a.sel (REG: a list of cells without FINER or WALL faces).
+// a.sel (REG: a list of cells without FINER or WALL faces).  MU: MUSCL, the
+// branch-free code for the cells whose stencil values are single rows, the
+// general code for the others (uniform branch).
 template <typename F, int NH, int T, int WPE, int FENCE, bool NT, bool MU = false, bool REG = false>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_step(StepArgs a) {
     static_assert(T % 64 == 0, "whole waves: the wave sums read every lane");
     __shared__ StepSmem<F, NH, T> sm;
     const uint32_t b = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const int64_t c = a.sel ? int64_t(as_const_space(a.sel)[b]) : int64_t(b);
-    if constexpr (!MU && !REG) {
+    if constexpr (MU) {
+        if (muscl_single_row(a.cells, c)) step_cell<F, NH, T, FENCE, NT, 2, true>(a, c, sm);
+        else step_cell<F, NH, T, FENCE, NT, 1, false>(a, c, sm);
+    } else if constexpr (!REG) {
         // every cell in one launch: the reduced code for the cells without
         // FINER or WALL faces, the full code for the others (uniform branch)
         if (needs_correction(a.cells, c)) step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
         else step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
     } else {
-        step_cell<F, NH, T, FENCE, NT, MU, REG>(a, c, sm);
+        step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
     }
 }
 
@@ -761,103 +1057,6 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     const int64_t c = int64_t(b - start);
     if (needs_correction(a.cells, c)) step_cell<F, NH, T, FENCE, NT, false, false>(a, c, sm);
     else step_cell<F, NH, T, FENCE, NT, false, true>(a, c, sm);
-}
-
-// MUSCL-minmod face values of the state a.f_in, three planes [3][n][NV] at
-// a.face (the paper is silent on the reconstruction; the reading: per cell,
-// axis b and velocity, sigma = minmod((f - fm)/dm, (fp - f)/dp) with fm, fp
-// the low- and high-side face-neighbour values -- the neighbour's average
-// (SAME, COARSER), the mean of the four finer leaves (FINER), the inflow
-// ghost (INFLOW) or the cell's own value (OUTFLOW) -- and dm, dp the centre
-// distances h, 3h/4 (FINER), 3h/2 (COARSER); sigma = 0 in a cell that touches
-// a wall).  Plane b holds the value at the face the velocity leaves through,
-//   D_b = f + sgn(xi_b) (h/2) sigma_b,
-// which is both the cell's outgoing value and the value its downwind
-// neighbour receives through that face.
-template <typename F, int NH>
-__global__ __launch_bounds__(256) void k_face(StepArgs a) {
-    constexpr int B = NH * NH * NH;
-    constexpr int64_t NV = 8 * B;
-    constexpr int T = 256;
-    // velocities per thread in one batch: every load of a batch is issued
-    // before the first is used, so a thread has 7-25 loads in flight instead
-    // of one velocity's
-    constexpr int U = 6;
-    // the XCD-aware order of the step kernel: a face neighbour's row, read by
-    // several workgroups, is more often still in the same L2
-    const int64_t c = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
-    const CellView cell(a.cells, c);
-    const F *__restrict__ fin = static_cast<const F *>(a.f_in);
-    F *__restrict__ face = static_cast<F *>(const_cast<void *>(a.face));
-    const F *own = fin + c * NV;
-    const double h = a.h0 / double(1 << cell.level());
-    const bool wall = cell.flags() & 1;
-    // per face: up to four source rows, their count and the centre distance
-    const F *src[6][4];
-    int cnt[6];
-    F dist[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        const int ty = cell.type(f);
-        cnt[f] = 1;
-        src[f][0] = src[f][1] = src[f][2] = src[f][3] = own;  // OUTFLOW (and WALL: unused)
-        dist[f] = F(h);
-        if (ty == DVM_FACE_SAME || ty == DVM_FACE_COARSER) {
-            src[f][0] = fin + int64_t(cell.nbr(f, 0)) * NV;
-            if (ty == DVM_FACE_COARSER) dist[f] = F(1.5 * h);
-        } else if (ty == DVM_FACE_FINER) {
-            cnt[f] = 4;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) src[f][k] = fin + int64_t(cell.nbr(f, k)) * NV;
-            dist[f] = F(0.75 * h);
-        } else if (ty == DVM_FACE_INFLOW) {
-            src[f][0] = static_cast<const F *>(a.ghost_in);
-        }
-    }
-    for (int64_t v0 = threadIdx.x; v0 < NV; v0 += int64_t(U) * T) {
-        F fc[U], nm[U][6];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t v = v0 + int64_t(u) * T;
-            fc[u] = v < NV ? own[v] : F(0);
-        }
-        if (!wall) {
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                if (cnt[f] == 4) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int64_t v = v0 + int64_t(u) * T;
-                        nm[u][f] = v < NV ? F(0.25) * (((src[f][0][v] + src[f][1][v]) + src[f][2][v]) + src[f][3][v])
-                                          : F(0);
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int64_t v = v0 + int64_t(u) * T;
-                        nm[u][f] = v < NV ? src[f][0][v] : F(0);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t v = v0 + int64_t(u) * T;
-            if (v >= NV) continue;
-            const int o = int(v / B);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                F sig = F(0);
-                if (!wall) {
-                    const F sl = (fc[u] - nm[u][2 * b]) / dist[2 * b], sr = (nm[u][2 * b + 1] - fc[u]) / dist[2 * b + 1];
-                    sig = sl * sr <= F(0) ? F(0) : (fabs(sl) < fabs(sr) ? sl : sr);
-                }
-                const int sb = b == 0 ? (o >> 2) : b == 1 ? ((o >> 1) & 1) : (o & 1);
-                const F half = F(sb ? 0.5 * h : -0.5 * h);
-                face[(b * a.n_cells + c) * NV + v] = fc[u] + half * sig;
-            }
-        }
-    }
 }
 
 // f := corrected Maxwellian of a prescribed state (init and ghost rows).
@@ -971,19 +1170,20 @@ __global__ __launch_bounds__(256) void k_wall_den(const F *m1, double *den, VelG
     X(8, 256, 5, 0)        \
     X(12, 192, 3, 1)
 
-// MUSCL step kernels: one shape per N
+// MUSCL step kernels: one shape per N, (NH, threads, waves per EU for FP32
+// and for FP64 storage, octant fence)
 #define DVM_MUSCL_CONFIGS(X) \
-    X(2, 64, 4, 0)           \
-    X(4, 64, 5, 0)           \
-    X(6, 256, 6, 0)          \
-    X(8, 256, 5, 0)          \
-    X(12, 192, 3, 1)
+    X(2, 64, 3, 3, 0)        \
+    X(4, 64, 3, 3, 0)        \
+    X(6, 256, 6, 6, 0)       \
+    X(8, 256, 5, 5, 0)       \
+    X(12, 576, 7, 3, 1)
 
 template <typename F>
 hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t st) {
     const dim3 grid(unsigned(a.sel ? a.n_sel : a.n_cells));
     if (cfg.regular) {
-        if (!a.sel || a.face) return hipErrorInvalidValue;
+        if (!a.sel || a.muscl) return hipErrorInvalidValue;
 #define X(NH, T, W, FN)                                                                                     \
         if (a.g.nh == NH && cfg.threads == T && (cfg.wpe == 0 || cfg.wpe == 10 * W + FN)) {                 \
             if (cfg.nt_store) hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true, false, true>), grid, dim3(T), 0, st, a); \
@@ -994,11 +1194,17 @@ hipError_t step_dispatch(const StepArgs &a, const StepConfig &cfg, hipStream_t s
 #undef X
         return hipErrorInvalidValue;
     }
-    if (a.face) {
-#define X(NH, T, W, FN)                                                                        \
-        if (a.g.nh == NH) {                                                                    \
-            hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true, true>), grid, dim3(T), 0, st, a); \
-            return hipGetLastError();                                                          \
+    if (a.muscl) {
+        // the shape asked for when the table has it, else the first listed for N
+        bool listed = false;
+#define X(NH, T, W32, W64, FN) listed |= a.g.nh == NH && cfg.threads == T;
+        DVM_MUSCL_CONFIGS(X)
+#undef X
+#define X(NH, T, W32, W64, FN)                                                                         \
+        if (a.g.nh == NH && (!listed || cfg.threads == T)) {                                           \
+            constexpr int W = sizeof(F) == 4 ? W32 : W64;                                              \
+            hipLaunchKernelGGL((k_step<F, NH, T, W, FN, true, true>), grid, dim3(T), 0, st, a);        \
+            return hipGetLastError();                                                                  \
         }
         DVM_MUSCL_CONFIGS(X)
 #undef X
@@ -1063,20 +1269,6 @@ inline bool step_config_exists(int nh, int threads, int wpe) {
     DVM_STEP_CONFIGS(X)
 #undef X
     return false;
-}
-
-template <typename F>
-hipError_t face_dispatch(const StepArgs &a, hipStream_t st) {
-    const dim3 grid(unsigned(a.n_cells)), blk(256);
-    switch (a.g.nh) {
-    case 2: hipLaunchKernelGGL((k_face<F, 2>), grid, blk, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_face<F, 4>), grid, blk, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((k_face<F, 6>), grid, blk, 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_face<F, 8>), grid, blk, 0, st, a); break;
-    case 12: hipLaunchKernelGGL((k_face<F, 12>), grid, blk, 0, st, a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 template <typename F>
