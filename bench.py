@@ -66,10 +66,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+SCHEME_OVERRIDE = None  # --scheme: the workload's mesh and flow with the other transport scheme
+WORKLOAD_ARG = None
+
+
 def build_case(name):
     from paper_1503_00707_amd import dvm as D
     from paper_1503_00707_amd import inputs as I
     w = I.workload(name)
+    if SCHEME_OVERRIDE is not None and name == WORKLOAD_ARG:
+        import dataclasses as dc
+        w = dc.replace(w, scheme=SCHEME_OVERRIDE)
     lev, ijk = D.balance(w.forest)
     import dataclasses
     forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
@@ -534,9 +541,15 @@ def main():
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline (no FP64, batch and hybrid legs)")
     ap.add_argument("--shape", default="", help="threads,wpe,xcd_group,nt_store of the step kernel")
+    ap.add_argument("--scheme", default="", choices=["", "upwind1", "muscl"],
+                    help="run the workload with this transport scheme instead of its own")
     ap.add_argument("--copy-calibration-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (read + write), for counter calibration")
     args = ap.parse_args()
+    global SCHEME_OVERRIDE, WORKLOAD_ARG
+    WORKLOAD_ARG = args.workload
+    if args.scheme:
+        SCHEME_OVERRIDE = 1 if args.scheme == "muscl" else 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -579,7 +592,8 @@ def main():
     copy_gbs = copy_ceiling()
     log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
     secondary, r64, rb, rk, rl = {}, None, None, None, None
-    headline_default = args.workload == "octree64_v24_p40" and args.precision == "fp32" and not args.shape
+    headline_default = (args.workload == "octree64_v24_p40" and args.precision == "fp32" and not args.shape
+                        and not args.scheme)
     if not args.no_secondary and headline_default:
         # the other precisions and modes of the metric, each after the headline's buffers are freed
         r64 = gpu_bench(args, precision="fp64", steps=3, warmup=1)
