@@ -63,13 +63,18 @@ def _samples(name, forest, tables, rng):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name,steps,precision", [("octree64_v24_p40", 10, D.PREC_FP32),
-                                                   ("sphere32_v24_muscl", 8, D.PREC_FP32),
-                                                   ("octree64_v24_p20", 10, D.PREC_FP64)])
-def test_full_size_sampled_cells_match_oracle(name, steps, precision):
+@pytest.mark.parametrize("name,steps,precision,scheme", [("octree64_v24_p40", 10, D.PREC_FP32, None),
+                                                          ("sphere32_v24_muscl", 8, D.PREC_FP32, None),
+                                                          ("octree64_v24_p20", 10, D.PREC_FP64, None),
+                                                          ("octree64_v24_p40", 3, D.PREC_FP32, I.SCHEME_MUSCL)])
+def test_full_size_sampled_cells_match_oracle(name, steps, precision, scheme):
+    """scheme: the workload's own, or MUSCL on the paper-scale octree (level
+    jumps within two hops of almost every cell: the step's general path)"""
     import torch
     t0 = time.time()
     w = I.workload(name)
+    if scheme is not None:
+        w = dataclasses.replace(w, scheme=scheme)
     lev, ijk = O.balance(w.forest)
     forest = dataclasses.replace(w.forest, level=lev, ijk=ijk)
     solid = None
