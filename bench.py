@@ -33,6 +33,9 @@ FP64_VECTOR_PEAK_TFS = 78.6
 KERNEL_SOURCES = ["paper_1503_00707_amd/csrc/step_impl.h", "paper_1503_00707_amd/csrc/kernels.h",
                   "paper_1503_00707_amd/csrc/kernels_f32.hip", "paper_1503_00707_amd/csrc/solver.cpp"]
 TRAFFIC_PROFILE = "profiles/k_step_fused_octree64_v24_p40_fp32.md"
+# counter profiles per workload (FP32, default launch shape, the workload's own scheme)
+TRAFFIC_PROFILES = {"octree64_v24_p40": TRAFFIC_PROFILE,
+                    "sphere32_v24_muscl": "profiles/k_step_muscl_sphere32_v24_fp32.md"}
 
 
 def kernel_source_hash():
@@ -44,10 +47,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_bytes):
+def measured_traffic(n_launch_bytes, profile=TRAFFIC_PROFILE):
     """HBM bytes per launch from the committed counter profile, if it was
     taken on the current kernel source (else None)"""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -58,7 +61,7 @@ def measured_traffic(n_launch_bytes):
             return dict(read_bytes=t["read_bytes"], write_bytes=t["write_bytes"],
                         total_bytes=t["read_bytes"] + t["write_bytes"],
                         vs_algorithmic=(t["read_bytes"] + t["write_bytes"]) / n_launch_bytes,
-                        source=TRAFFIC_PROFILE)
+                        source=profile)
     return None
 
 
@@ -655,7 +658,8 @@ def main():
     w = r["w"]
     ms = r["total_ms"] / args.steps
     # the committed counter profile covers the default workload and launch shape only
-    traffic = measured_traffic(r["alg_bytes"]) if headline_default else None
+    profiled = args.precision == "fp32" and not args.shape and not args.scheme and args.workload in TRAFFIC_PROFILES
+    traffic = measured_traffic(r["alg_bytes"], TRAFFIC_PROFILES[args.workload]) if profiled else None
     out = {
         "metric": METRIC,
         "value": r["cvu"],
