@@ -781,14 +781,6 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
     } else {
         // runtime loops over octants and axes (one copy of the code); the
         // register arrays are reached through uniform selects, never indexed
-        F nu[3][S];
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            int a3[3];
-            ln.axes(q, a3[0], a3[1], a3[2]);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) nu[b][q] = F(dth) * (F(a3[b]) + F(0.5)) * F(a.g.dv[b]);
-        }
         const RecRT rc(a.cells, c);
         const bool wall = cell.flags() & 1;
 #pragma nounroll
@@ -844,7 +836,11 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
                 }
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
-                    const F nub = b == 0 ? nu[0][q] : b == 1 ? nu[1][q] : nu[2][q];
+                    int a3[3];
+                    ln.axes_late(q, a3[0], a3[1], a3[2]);
+                    const int ab = b == 0 ? a3[0] : b == 1 ? a3[1] : a3[2];
+                    const double dvb = b == 0 ? a.g.dv[0] : b == 1 ? a.g.dv[1] : a.g.dv[2];
+                    const F nub = F(dth) * (F(ab) + F(0.5)) * F(dvb);
                     t[q] += nub * (dc[q] - in[q]);
                 }
             }
