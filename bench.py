@@ -47,9 +47,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_bytes, profile=TRAFFIC_PROFILE):
-    """HBM bytes per launch from the committed counter profile, if it was
-    taken on the current kernel source (else None)"""
+def measured_traffic(n_launch_bytes, profile=None):
+    """HBM bytes per launch from the committed counter profile (the
+    headline's unless another is named), if it was taken on the current
+    kernel source (else None)"""
+    profile = profile or TRAFFIC_PROFILE
     path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None

@@ -31,3 +31,17 @@ def test_stored_traffic_follows_the_kernel_source_hash(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0000000000000000")
     assert bench.measured_traffic(200) is None
 
+
+
+def test_every_workload_traffic_profile_holds_counters_of_the_current_source():
+    """each committed per-workload counter profile exists, carries one
+    traffic_json record, and was taken on the step source in the tree (else
+    the bench line would report traffic as null)"""
+    for workload, rel in bench.TRAFFIC_PROFILES.items():
+        path = os.path.join(ROOT, rel)
+        assert os.path.exists(path), rel
+        recs = [json.loads(l.split(":", 1)[1]) for l in open(path) if l.startswith("traffic_json:")]
+        assert len(recs) == 1, rel
+        assert recs[0]["source_sha256"] == bench.kernel_source_hash(), (workload, rel)
+        assert recs[0]["read_bytes"] > 0 and recs[0]["write_bytes"] > 0
+        assert bench.measured_traffic(1, rel) is not None
