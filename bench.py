@@ -372,14 +372,16 @@ def _moment_scale(mom):
 def _cone_oracle(r, threads, log_every=True):
     """The FP64 oracle on the face-hop cone of the sampled cells of a GPU run
     (eq. 2 couples a cell to its face neighbours only, so after k steps a cell
-    depends on the cells within k hops): run for the same steps from the same
-    initial state.  Returns (moment error, f error, CVU, seconds, rows)."""
+    depends on the cells within k hops, 2k with MUSCL, whose slopes read the
+    neighbours' neighbours): run for the same steps from the same initial
+    state.  Returns (moment error, f error, CVU, seconds, rows)."""
     from oracle import oracle as O
     from paper_1503_00707_amd import inputs as I
     w, forest, solid, smp = r["w"], r["forest"], r["solid"], r["samples"]
     om = O.Mesh(forest, solid)
     ot = om.tables()
-    cells = om.cone(smp["cells"], smp["steps"])
+    hops = smp["steps"] * (2 if w.scheme == I.SCHEME_MUSCL else 1)
+    cells = om.cone(smp["cells"], hops)
     op = O.make_params(w.nv, w.vlo, w.vhi, scheme=w.scheme, collision=w.collision, tau_mode=w.tau_mode,
                        tau_or_kn=w.tau_or_kn, inflow=w.inflow, t_wall=w.t_wall, korobov_p=w.korobov_p)
     osub = O.Solver(om, op, cells)
@@ -460,9 +462,10 @@ def cpu_leg(head, fp64=None, batch=None, korobov=None, lbm=None):
     O.set_threads(cores)
     em, ef, cvu, secs, rows = _cone_oracle(head, cores)
     w = head["w"]
+    hops = head["samples"]["steps"] * (2 if w.scheme == 1 else 1)
     cpu = dict(value=cvu / secs, unit="CVU/s", cores=int(O.get_threads()), kind="oracle",
                sample=f"{head['samples']['cells'].size} sampled cells of {w.name} and their "
-                      f"{head['samples']['steps']}-hop face cone: {rows} cells x {int(np.prod(w.nv))} velocities, "
+                      f"{hops}-hop face cone: {rows} cells x {int(np.prod(w.nv))} velocities, "
                       f"FP64, {head['samples']['steps']} steps, {secs:.1f}s")
     errors = {"fp32_headline": dict(moments=em, f=ef, cells=int(head["samples"]["cells"].size),
                                     steps=int(head["samples"]["steps"]))}
