@@ -451,7 +451,7 @@ def _cone_oracle_lbm(r):
     return em, ef
 
 
-def cpu_leg(head, fp64=None, batch=None, korobov=None, lbm=None):
+def cpu_leg(head, fp64=None, batch=None, korobov=None, lbm=None, muscl=None):
     """The FP64 CPU oracle, timed on the host cores on a bounded sample of the
     headline workload (the face-hop cone of the sampled cells over all the
     steps the GPU took), which also gives the headline's error against the
@@ -477,6 +477,10 @@ def cpu_leg(head, fp64=None, batch=None, korobov=None, lbm=None):
         emk, efk, _, _, _ = _cone_oracle(korobov, cores, log_every=False)
         errors["korobov"] = dict(moments=emk, f=efk, cells=int(korobov["samples"]["cells"].size),
                                  steps=int(korobov["samples"]["steps"]))
+    if muscl is not None:
+        emm, efm, _, _, _ = _cone_oracle(muscl, cores, log_every=False)
+        errors["muscl_sphere32"] = dict(moments=emm, f=efm, cells=int(muscl["samples"]["cells"].size),
+                                        steps=int(muscl["samples"]["steps"]))
     if lbm is not None:
         eml, efl = _cone_oracle_lbm(lbm)
         errors["lbm_d3q19"] = dict(moments=eml, f=efl, cells=int(lbm["samples"]["cells"].size),
@@ -599,7 +603,7 @@ def main():
     r = gpu_bench(args)
     copy_gbs = copy_ceiling()
     log(f"[bench] plain device copy: {copy_gbs:.0f} GB/s")
-    secondary, r64, rb, rk, rl = {}, None, None, None, None
+    secondary, r64, rb, rk, rl, rm = {}, None, None, None, None, None
     headline_default = (args.workload == "octree64_v24_p40" and args.precision == "fp32" and not args.shape
                         and not args.scheme)
     if not args.no_secondary and headline_default:
@@ -658,8 +662,22 @@ def main():
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rq["achieved"] / HBM_PEAK_GBS,
                              "algorithmic_bytes_per_launch": rq["alg_bytes"], "kernel_ms_mean": rq["k_ms"]},
                 "status": int(rq["rc"])}
+        # the MUSCL configuration (Mach-2 sphere, walls, inflow and outflow, 58,768 cells x 24^3)
+        rm = gpu_bench(args, precision="fp32", steps=10, warmup=2, workload="sphere32_v24_muscl")
+        msm = rm["total_ms"] / rm["steps"]
+        tm = measured_traffic(rm["alg_bytes"], TRAFFIC_PROFILES["sphere32_v24_muscl"])
+        secondary["muscl_sphere32"] = {
+            "workload": "sphere32_v24_muscl", "cells": rm["n"], "velocities": rm["nv"], "scheme": "muscl-minmod",
+            "precision": "f stored FP32, moments/Maxwellian/correction FP64", "steps": rm["steps"], "warmup": 2,
+            "ms_per_step": msm, "value": rm["cvu"], "unit": "CVU/s",
+            "roofline": {"bound": "hbm", "kernel": rm["kernel"], "achieved": rm["achieved"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": rm["achieved"] / HBM_PEAK_GBS,
+                         "traffic": tm["total_bytes"] if tm else None, "traffic_detail": tm,
+                         "algorithmic_bytes_per_launch": rm["alg_bytes"],
+                         "kernel_ms_mean": float(np.mean(rm["k_ms"]))},
+            "status": int(rm["rc"])}
     cpu, errors = (None, None) if args.no_cpu_baseline else cpu_leg(
-        r, r64, rb, rk if secondary else None, rl if secondary else None)
+        r, r64, rb, rk if secondary else None, rl if secondary else None, rm if secondary else None)
     w = r["w"]
     ms = r["total_ms"] / args.steps
     # the committed counter profile covers the default workload and launch shape only
