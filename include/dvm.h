@@ -302,9 +302,11 @@ int dvm_tune_split(dvm_solver *s, int32_t enable, int32_t threads_irr, int32_t w
  * is rewritten through a temporary and renamed).  The trial steps read the
  * current state and write the other state buffer and the moments buffer; the
  * moments are then recomputed from the current state (within rounding of the
- * step's own values).  Synchronises.  DVM_ERR_UNSUPPORTED while fluid cells
- * of a hybrid step hold no f; DVM_ERR_ARG if the
- * cache cannot be written.
+ * step's own values).  Synchronises.  A MUSCL solver's step kernel has one
+ * shape per N (threads, waves per EU and non-temporal stores fixed): for it
+ * only the XCD grouping changes what runs.  DVM_ERR_UNSUPPORTED while fluid
+ * cells of a hybrid step hold no f; DVM_ERR_ARG if the cache cannot be
+ * written.
  */
 int dvm_tune(dvm_solver *s, const char *cache_path, int32_t reps, int32_t *from_cache, void *stream);
 
