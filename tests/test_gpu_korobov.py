@@ -62,3 +62,14 @@ def test_octree_korobov_open_boundaries_fp32():
     f = balanced(I.random_forest(8, (2, 2, 2), 2, 0.3, bc))
     case = _kcase(f, 8, 6.0, 127, kn=0.3, seed=5, inflow=(1.0, 0.8, 0.0, 0.0, 1.0), t_wall=1.2)
     _compare(case, 6, D.PREC_FP32, FP32_TOL)
+
+
+def test_octree_korobov_after_muscl_transport_fp64():
+    """the collision integral after a MUSCL transport (the step's MUSCL form
+    with the collision off, then the Korobov kernel), inflow, outflow and wall
+    faces on an octree"""
+    bc = (I.INFLOW, I.OUTFLOW, I.WALL, I.OUTFLOW, I.PERIODIC, I.PERIODIC)
+    f = balanced(I.random_forest(9, (2, 2, 2), 2, 0.3, bc))
+    case = _kcase(f, 8, 6.0, 127, kn=0.3, seed=7, scheme=I.SCHEME_MUSCL, inflow=(1.0, 0.8, 0.0, 0.0, 1.0),
+                  t_wall=1.2)
+    _compare(case, 4, D.PREC_FP64, FP64_TOL, f_tol=FP64_TOL)
