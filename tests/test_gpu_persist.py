@@ -159,6 +159,27 @@ def test_tune_persists_and_reuses_its_choice(tmp_path):
     assert [(g["nh"], g["threads"], g["wpe"], g["xcd_group"], g["nt_store"]) for g in bt2.groups()] == first
 
 
+def test_tune_a_muscl_solver_keeps_its_result(tmp_path):
+    """a MUSCL solver tunes under its own key (scheme=1): only the XCD
+    grouping changes what runs, and the tuned solver steps bitwise like an
+    untuned one"""
+    import torch
+    case = _case(I.SCHEME_MUSCL)
+    path = str(tmp_path / "tune.txt")
+    dm, a = gpu_solver(case, D.PREC_FP32)
+    assert a.tune(path, reps=1) is False
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and " fp64=0 scheme=1 | " in lines[0]
+    dm2, b = gpu_solver(case, D.PREC_FP32)
+    dt = a.dt(0.5)
+    a.init_maxwellian(np_prim(case, dm))
+    b.init_maxwellian(np_prim(case, dm2))
+    a.step(4, dt=dt)
+    b.step(4, dt=dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.f_canonical().cpu().numpy(), b.f_canonical().cpu().numpy())
+
+
 def np_prim(case, dm):
     from tests.gpu_common import prim_for
     return prim_for(case, dm.tables()["input"])
