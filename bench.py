@@ -511,7 +511,7 @@ def gpu_hybrid():
     shape (rho = 1 + 0.1 sin 2 pi x) at tau = 0.1 (the C1 flow) and 0.01
     (near continuum): on the C1 mesh (16^3 cells x 8^3 velocities) and on 32^3
     cells x 24^3 velocities, both sides replayed as HIP graphs; full DVM on the
-    same flow is the judge of the error, and the Kn_GLL criterion calibrated
+    same flow is the reference for the error, and the Kn_GLL criterion calibrated
     against the same bar runs beside the network.  Needs the committed
     trained sensor."""
     from paper_1503_00707_amd import dvm as D
@@ -563,7 +563,7 @@ def main():
     if args.scheme:
         SCHEME_OVERRIDE = 1 if args.scheme == "muscl" else 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_gb > 0:

@@ -215,7 +215,7 @@ def evaluate(net, kappa=None, fields="sine_rho", field_args=None, tau=0.1, steps
 
 
 # ---------------------------------------------------------------------------
-# calibration against the error bar: full DVM is the judge
+# calibration against the error bar: full DVM is the reference
 # ---------------------------------------------------------------------------
 
 def flow(seed, tau=None):

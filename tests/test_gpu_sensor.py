@@ -251,7 +251,7 @@ def test_trained_sensor_gains_over_the_method_without_it():
     kernels on DVM labels over relaxation times 0.001..1, decision threshold
     calibrated against the 1e-3 error bar; sensor_train.build_trained) gains
     over the Kn_GLL criterion calibrated the same way, with full DVM as the
-    judge of the error (20 steps):
+    reference for the error (20 steps):
     - on the C1 flow (16^3 cells x 8^3 velocities, rho = 1 + 0.1 sin 2 pi x)
       at tau = 0.01, 0.03 and 0.1 it stays within the bar, never keeps more
       cells kinetic than Kn_GLL, and keeps strictly fewer at two of them;
