@@ -357,10 +357,21 @@ def main(argv=None):
     ap.add_argument("--build", action="store_true",
                     help="calibrate, train and write the committed sensor (sensor_net.json)")
     ap.add_argument("--out", default=TRAINED)
+    ap.add_argument("--evaluate", action="store_true",
+                    help="the committed sensor's hybrid against plain DVM on one flow (graphs on both sides)")
+    ap.add_argument("--level", type=int, default=4, help="--evaluate: 2^level cells per side")
+    ap.add_argument("--nv", type=int, default=NV, help="--evaluate: velocities per axis")
+    ap.add_argument("--vmax", type=float, default=VMAX, help="--evaluate: velocity box half-width")
+    ap.add_argument("--tau", type=float, default=0.1, help="--evaluate: relaxation time")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+    if args.evaluate:
+        net, _ = load_trained()
+        r = evaluate(net, tau=args.tau, level=args.level, nv=args.nv, vmax=args.vmax, graph=True)
+        print(json.dumps(r), flush=True)
+        return r
     if args.build:
         _, meta = build_trained(runs=args.runs, epochs=args.epochs, log=log, path=args.out)
         print(json.dumps({k: v for k, v in meta.items() if not k.endswith("_table")}), flush=True)
