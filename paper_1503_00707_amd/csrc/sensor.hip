@@ -15,6 +15,7 @@ namespace {
 constexpr size_t kScratchRec = (size_t(kNoAllocMaxBatch) * kMlpRecord * sizeof(float) + 255) & ~size_t(255);
 constexpr size_t kScratchPart = (size_t((kNoAllocMaxBatch + 255) / 256) * sizeof(double) + 255) & ~size_t(255);
 constexpr int kMaxDevices = 64;
+constexpr int64_t kSensorSmallMesh = 65536;
 }  // namespace
 static __device__ __align__(256) char scratch[kScratchRec + kScratchPart];
 
@@ -69,8 +70,13 @@ hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, in
 
 hipError_t launch_sensor(const SensorArgsPub &a, const float *params, double kappa, uint8_t *mask, float *score,
                          hipStream_t st) {
-    hipLaunchKernelGGL(impl::k_sensor, dim3(unsigned((a.n + 63) / 64)), dim3(256), 0, st, feat(a), params, kappa,
-                       mask, score);
+    // below 1024 workgroups of 64 cells, one-wave workgroups of 16 cells
+    if (a.n <= kSensorSmallMesh)
+        hipLaunchKernelGGL(impl::k_sensor<16>, dim3(unsigned((a.n + 15) / 16)), dim3(64), 0, st, feat(a), params,
+                           kappa, mask, score);
+    else
+        hipLaunchKernelGGL(impl::k_sensor<64>, dim3(unsigned((a.n + 63) / 64)), dim3(256), 0, st, feat(a), params,
+                           kappa, mask, score);
     return hipGetLastError();
 }
 

@@ -76,8 +76,10 @@ __device__ inline void cell_features(const FeatArgs &a, int64_t c, double x[10])
     double q[5];
     prim5(a.mom, a.n, c, q);
     double g2[5] = {0, 0, 0, 0, 0};
+#pragma unroll
     for (int b = 0; b < 3; ++b) {
         double qs[2][5], ds[2];
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int f = 2 * b + side;
             const int ty = cell.type[f];
@@ -227,14 +229,15 @@ __device__ __forceinline__ short to_bf16(float v) {
     return short(u >> 16);
 }
 
-// Logits of 64 rows per workgroup (4 waves x 16 rows) on the matrix cores.
+// Logits of R rows per workgroup (R / 16 waves x 16 rows) on the matrix cores.
 // Operand layout of v_mfma_f32_16x16x16_bf16 for lane l: A[i = l % 16][k =
 // 4 (l / 16) + 0..3], B[k = 4 (l / 16) + 0..3][j = l % 16], result
 // D[i = 4 (l / 16) + v][j = l % 16], v = 0..3.  Hidden activations go through
 // LDS to turn the result layout into the next layer's A layout.
-// xs: standardised features [64][16] (columns >= 10 are zero), written by the
-// caller into LDS; out: logits of the 64 rows.
-__device__ inline void mlp_tile_mfma(const float *w, const float (&xs)[64][16], float (&h1)[4][16][kHid + 4],
+// xs: standardised features [R][16] (columns >= 10 are zero), written by the
+// caller into LDS; out: logits of the R rows.
+template <int R>
+__device__ inline void mlp_tile_mfma(const float *w, const float (&xs)[R][16], float (&h1)[R / 16][16][kHid + 4],
                                      float *out) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -293,25 +296,54 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_mfma(const float *P, const floa
         xs[r][k] = (k < kIn && s < n) ? (x[s * kIn + k] - w[kMean + k]) / w[kStd + k] : 0.0f;
     }
     __syncthreads();
-    mlp_tile_mfma(w, xs, h1, out);
+    mlp_tile_mfma<64>(w, xs, h1, out);
     __syncthreads();
     if (threadIdx.x < 64 && r0 + threadIdx.x < n) z[r0 + threadIdx.x] = out[threadIdx.x];
 }
 
-// The sensor: features of 64 cells per workgroup, then the network on the
-// matrix cores (mlp != nullptr) or the largest gradient-length Knudsen
-// number against kappa.  mask = 1: kinetic.
-__global__ __launch_bounds__(256) void k_sensor(FeatArgs a, const float *P, double kappa, uint8_t *mask,
-                                                float *score) {
-    __shared__ float w[kParams];
-    __shared__ float xs[64][16];
-    __shared__ float h1[4][16][kHid + 4];
-    __shared__ float out[64];
-    const int64_t c0 = int64_t(blockIdx.x) * 64;
-    if (P)
-        for (int i = threadIdx.x; i < kParams; i += 256) w[i] = P[i];
+// Copy the parameter block to LDS with NT threads: 16-byte loads, all in
+// flight before the first LDS store (a 64-thread workgroup would otherwise
+// wait out some 80 dependent round trips); element loads when P is not
+// 16-byte aligned.  w must be 16-byte aligned.  The tail lanes re-read the
+// last vector instead of branching around the load, which keeps the staging
+// registers out of scratch.
+template <int NT>
+__device__ inline void stage_params(float *w, const float *P) {
+    constexpr int n4 = kParams / 4, per = (n4 + NT - 1) / NT;
+    if ((reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+        const float4 *P4 = reinterpret_cast<const float4 *>(P);
+        float4 *w4 = reinterpret_cast<float4 *>(w);
+        float4 r[per];
+#pragma unroll
+        for (int k = 0; k < per; ++k) r[k] = P4[min(int(threadIdx.x) + k * NT, n4 - 1)];
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < n4) w4[i] = r[k];
+        }
+        for (int i = 4 * n4 + threadIdx.x; i < kParams; i += NT) w[i] = P[i];
+    } else {
+        for (int i = threadIdx.x; i < kParams; i += NT) w[i] = P[i];
+    }
+}
+
+// The sensor: features of R cells per workgroup (one thread each; the
+// workgroup has R / 16 waves), then the network on the matrix cores
+// (mlp != nullptr) or the largest gradient-length Knudsen number against
+// kappa.  mask = 1: kinetic.  R = 16 spreads a small mesh over more compute
+// units; a row's result does not depend on R.
+template <int R>
+__global__ __launch_bounds__(4 * R) void k_sensor(FeatArgs a, const float *P, double kappa, uint8_t *mask,
+                                                  float *score) {
+    static_assert(R == 16 || R == 64, "rows per workgroup");
+    __shared__ __align__(16) float w[kParams];
+    __shared__ float xs[R][16];
+    __shared__ float h1[R / 16][16][kHid + 4];
+    __shared__ float out[R];
+    const int64_t c0 = int64_t(blockIdx.x) * R;
+    if (P) stage_params<4 * R>(w, P);
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < R) {
         const int64_t c = c0 + threadIdx.x;
         double f[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (c < a.n) cell_features(a, c, f);
@@ -325,9 +357,9 @@ __global__ __launch_bounds__(256) void k_sensor(FeatArgs a, const float *P, doub
         }
     }
     __syncthreads();
-    if (P) mlp_tile_mfma(w, xs, h1, out);
+    if (P) mlp_tile_mfma<R>(w, xs, h1, out);
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < R) {
         const int64_t c = c0 + threadIdx.x;
         if (c < a.n) {
             const float v = out[threadIdx.x];

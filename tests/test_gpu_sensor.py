@@ -120,10 +120,31 @@ def test_normalization_statistics():
     assert np.allclose(got[I.MLP_WEIGHTS + 10:], xd.std(0), rtol=1e-6)
 
 
-def test_sensor_masks_match_oracle():
+def _sensor_case(big):
+    """(forest, oracle tables, oracle solver, library solver): a few hundred
+    cells after three steps, or a 110,592-cell uniform mesh at its initial
+    state (above 65,536 cells the sensor runs 64 cells per workgroup, below
+    that 16)"""
+    if not big:
+        f = _case(seed=5)
+        om, ot, op, os_, dm, s, dt = _pair(f, 3, tau=0.2)
+        return f, ot, os_, s
+    f = I.uniform_forest((6, 6, 6), 3)
+    om = O.Mesh(f)
+    ot = om.tables()
+    os_ = O.Solver(om, O.make_params((4,) * 3, (-4.0,) * 3, (4.0,) * 3, tau_mode=I.TAU_CONST, tau_or_kn=0.2))
+    os_.init_maxwellian(I.fields("sines", I.leaf_centres(f)[ot["input"]], seed=9))
+    dm = D.Mesh(f)
+    s = D.Solver(dm, D.make_params(4, 4.0, precision=D.PREC_FP64, tau_mode=I.TAU_CONST, tau_or_kn=0.2))
+    s.init_maxwellian(I.fields("sines", I.leaf_centres(f)[dm.tables()["input"]], seed=9))
+    assert s.n > 65536
+    return f, ot, os_, s
+
+
+@pytest.mark.parametrize("big", [False, True], ids=["small", "110592_cells"])
+def test_sensor_masks_match_oracle(big):
     import torch
-    f = _case(seed=5)
-    om, ot, op, os_, dm, s, dt = _pair(f, 3, tau=0.2)
+    f, ot, os_, s = _sensor_case(big)
     xo = S.features(os_.moments(), ot, f.h0, 0, 0.2)
     kappa = float(np.median(S.kn_gll(xo)))
     mask, score = s.sensor(None, kappa)
