@@ -29,9 +29,9 @@ the readings stated below):
     keeps only the moments of its transported g, which is the kinetic
     flux-vector-splitting update U - dt/V sum_faces A (H+(g_own) + H-(g_up))
     with the half-range fluxes of the discrete velocity set.
-  * closed_half_flux() (parity unpinned by the paper, which names the
-    closed-form half-Maxwellian fluxes without printing them; pinned by
-    quadrature of the defining integral and by the Euler flux identity):
+  * closed_half_flux() (the paper names the closed-form half-Maxwellian
+    fluxes without printing them; pinned by quadrature of the defining
+    integral and by the Euler flux identity):
     the half-range integral over xi_b > 0 or < 0 of xi_b (1, xi, |xi|^2/2)
     times the continuous Maxwellian of U; Hybrid(flux="closed") uses it on
     faces between two fluid cells in place of the discrete half-range sums
