@@ -143,6 +143,18 @@ __device__ __forceinline__ Rsrc rsrc(const void *p, uint32_t bytes) {
     void *u = reinterpret_cast<void *>((uint64_t(hi) << 32) | lo);
     return __builtin_amdgcn_make_buffer_rsrc(u, short(0), int(bytes), kRsrcWord3);
 }
+// A workgroup-uniform value read by every lane (from LDS, say), moved to
+// scalar registers.
+__device__ __forceinline__ float uniform_value(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, x)));
+}
+__device__ __forceinline__ double uniform_value(double x) {
+    const uint64_t v = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
 template <typename F>
 __device__ __forceinline__ F bld(Rsrc r, uint32_t voff, uint32_t soff);
 template <>
@@ -600,8 +612,8 @@ struct RecRT {
     __device__ __forceinline__ int flags() const { return p[25] >> 24; }
 };
 
-// Every face of the cell is SAME, INFLOW or OUTFLOW, and behind no SAME face
-// lies a FINER face: each value its MUSCL stencil reads is one row (the
+// Every face of the cell is SAME, INFLOW, OUTFLOW or WALL, and behind no SAME
+// face lies a FINER face: each value its MUSCL stencil reads is one row (the
 // branch-free code).
 __device__ __forceinline__ bool muscl_single_row(const DevCell *cells, int64_t c) {
     const RecRT r(cells, c);
@@ -610,7 +622,7 @@ __device__ __forceinline__ bool muscl_single_row(const DevCell *cells, int64_t c
     for (int f = 0; f < 6; ++f) {
         const int ty = r.type(f);
         if (ty == DVM_FACE_SAME) ok &= RecRT(cells, r.nbr(f, 0)).type(f) != DVM_FACE_FINER;
-        else ok &= ty == DVM_FACE_INFLOW || ty == DVM_FACE_OUTFLOW;
+        else ok &= ty == DVM_FACE_INFLOW || ty == DVM_FACE_OUTFLOW || ty == DVM_FACE_WALL;
     }
     return ok;
 }
@@ -686,9 +698,12 @@ __device__ __forceinline__ void muscl_face_value(const StepArgs &a, int64_t x, i
 //   FAST: the cells of muscl_single_row: per face the neighbour row and the
 //         row behind the neighbour, selected once per cell; the loads of an
 //         octant are independent of each other and issued together;
+//         WALLS: such a cell with a diffuse-wall face (no slope of its own;
+//         through a wall face enters rho_w times the wall Maxwellian), whose
+//         wall densities are in rho_w;
 //   else: any cell (level jumps on either hop, walls): the stencil is read
 //         from the neighbours' records, axis by axis.
-template <typename F, int NH, int T, bool FAST, bool LATE_OWN>
+template <typename F, int NH, int T, bool FAST, bool LATE_OWN, bool WALLS = false>
 __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellView &cell, int64_t c,
                                                 const Rsrc &own, const StepArgs &a, const double *rho_w, double dth,
                                                 double (&m)[5]) {
@@ -703,7 +718,8 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
     const F hh = F(0.5 * h), ih = F(1.0 / h);
     if constexpr (FAST) {
         // per face f: the cell whose row lies across f (the inflow ghost: -1;
-        // an OUTFLOW face: the cell itself) and, behind a SAME neighbour u,
+        // the wall Maxwellian: -2; an OUTFLOW face: the cell itself) and,
+        // behind a SAME neighbour u,
         // the next one along the axis (u itself at an OUTFLOW or WALL face);
         // 1/distance from u to that one; whether u has a slope (SAME and not
         // touching a wall)
@@ -712,7 +728,10 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
             const int ty = cell.type(f);
-            Ni[f] = ty == DVM_FACE_SAME ? cell.nbr(f, 0) : ty == DVM_FACE_INFLOW ? -1 : int32_t(c);
+            Ni[f] = ty == DVM_FACE_SAME     ? cell.nbr(f, 0)
+                    : ty == DVM_FACE_INFLOW ? -1
+                    : ty == DVM_FACE_WALL   ? -2
+                                            : int32_t(c);
             Fi[f] = Ni[f];
             if (ty == DVM_FACE_SAME) {
                 const RecRT u(a.cells, Ni[f]);
@@ -727,9 +746,10 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
         // and without branches: a select inside the loop becomes a branch,
         // and the compiler then hoists every octant's loads and spills them
         const uint64_t ghost = reinterpret_cast<uint64_t>(a.ghost_in), base = reinterpret_cast<uint64_t>(fin);
+        const uint64_t wallm = reinterpret_cast<uint64_t>(a.wall_m1);
         const auto row = [&](int32_t i) {
             const uint64_t at = base + uint64_t(int64_t(i < 0 ? 0 : i) * NV * int64_t(sizeof(F)));
-            return rsrc(reinterpret_cast<const void *>(i < 0 ? ghost : at), kRow);
+            return rsrc(reinterpret_cast<const void *>(i < 0 ? (i == -1 ? ghost : wallm) : at), kRow);
         };
         const F i15 = F(1.0 / (1.5 * h));
         Rsrc RN[6], RF[6];
@@ -741,6 +761,51 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
             ifar[f] = (farc >> f) & 1u ? i15 : ih;
             son[f] = (on >> f) & 1u ? F(1) : F(0);
         }
+        if constexpr (WALLS) {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
+                // rho_w on a wall face, 1 on the others (an exact product);
+                // read per octant, after the fence, to keep them out of the
+                // registers the loads need
+                F sN[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) sN[b] = uniform_value(F(rho_w[sg[b] ? 2 * b : 2 * b + 1]));
+                F up[3][S], far[3][S];
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const uint32_t so = L::template soff<F>(o, q);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int fu = sg[b] ? 2 * b : 2 * b + 1;
+                        up[b][q] = bld<F>(RN[fu], voff, so);
+                        far[b][q] = bld<F>(RF[fu], voff, so);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    int a3[3];
+                    ln.axes_late(q, a3[0], a3[1], a3[2]);
+                    const F v = fo[o][q];
+                    F t = F(0);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const int fu = sg[b] ? 2 * b : 2 * b + 1;
+                        const F half = sg[b] ? hh : -hh;
+                        // son is 0 on a wall face: there the slope drops out
+                        // and din is rho_w times the wall row
+                        const F u = up[b][q];
+                        const F su = sg[b] ? minmod((u - far[b][q]) * ifar[fu], (v - u) * ih)
+                                           : minmod((u - v) * ih, (far[b][q] - u) * ifar[fu]);
+                        const F din = sN[b] * u + half * (son[fu] * su);
+                        const F nub = F(dth) * (F(a3[b]) + F(0.5)) * F(a.g.dv[b]);
+                        t += nub * (v - din);  // a wall cell has no slope of its own
+                    }
+                    fo[o][q] = v - t;
+                }
+                asm volatile("" ::: "memory");  // one octant's loads in flight at a time
+            }
+        } else {
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const int sg[3] = {o >> 2, (o >> 1) & 1, o & 1};
@@ -777,6 +842,7 @@ __device__ __forceinline__ void transport_muscl(Regs<F, NH, T> &fo, const CellVi
                 fo[o][q] = v - t;
             }
             asm volatile("" ::: "memory");  // one octant's loads in flight at a time
+        }
         }
     } else {
         // runtime loops over octants and axes (one copy of the code); the
@@ -902,7 +968,10 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
     if (!REG && (cell.flags() & 1)) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if (cell.type(f) != DVM_FACE_WALL) continue;
+            if (cell.type(f) != DVM_FACE_WALL) {
+                if (tid == 0) sm.rho_w[f] = 1.0;  // the MUSCL wall-cell path scales every face
+                continue;
+            }
             const int axis = f >> 1, side = f & 1;
             double v[1] = {0.0};
 #pragma unroll
@@ -931,7 +1000,7 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
 
     double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (MU) {
-        transport_muscl<F, NH, T, MU == 2, kLateOwn>(fo, cell, c, own, a, sm.rho_w, dth, m);
+        transport_muscl<F, NH, T, MU == 2, kLateOwn, MU == 2 && !REG>(fo, cell, c, own, a, sm.rho_w, dth, m);
     } else {
         // one row descriptor per face for the main transport pass: the upwind
         // cell's average
@@ -1017,8 +1086,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(WPE, 8))) voi
     const uint32_t b = remap_cell(blockIdx.x, gridDim.x, a.xcd_log2);
     const int64_t c = a.sel ? int64_t(as_const_space(a.sel)[b]) : int64_t(b);
     if constexpr (MU) {
-        if (muscl_single_row(a.cells, c)) step_cell<F, NH, T, FENCE, NT, 2, true>(a, c, sm);
-        else step_cell<F, NH, T, FENCE, NT, 1, false>(a, c, sm);
+        if (!muscl_single_row(a.cells, c)) step_cell<F, NH, T, FENCE, NT, 1, false>(a, c, sm);
+        else if (RecRT(a.cells, c).flags() & 1) step_cell<F, NH, T, FENCE, NT, 2, false>(a, c, sm);
+        else step_cell<F, NH, T, FENCE, NT, 2, true>(a, c, sm);
     } else if constexpr (!REG) {
         // every cell in one launch: the reduced code for the cells without
         // FINER or WALL faces, the full code for the others (uniform branch)
