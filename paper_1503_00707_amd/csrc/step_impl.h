@@ -964,14 +964,16 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, int64_t c, StepSmem
             for (int o = 0; o < 8; ++o) fo[o][q] = bld<F>(own, voff, L::template soff<F>(o, q));
     }
 
+    // the MUSCL wall-cell path scales the row across every face: 1 where no
+    // wall is (the wall faces' densities follow, after barriers)
+    if constexpr (MU == 2 && !REG) {
+        if (tid < 6) sm.rho_w[tid] = 1.0;
+    }
     // diffuse walls: density of the re-emitted Maxwellian (zero net mass flux)
     if (!REG && (cell.flags() & 1)) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            if (cell.type(f) != DVM_FACE_WALL) {
-                if (tid == 0) sm.rho_w[f] = 1.0;  // the MUSCL wall-cell path scales every face
-                continue;
-            }
+            if (cell.type(f) != DVM_FACE_WALL) continue;
             const int axis = f >> 1, side = f & 1;
             double v[1] = {0.0};
 #pragma unroll
